@@ -1,0 +1,104 @@
+"""FP64 CPU oracle of the learned cost model and beam selection.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline use it to check and time the GPU library.  The product path never
+imports it; the two share no code.
+
+Python side: ctypes marshalling of numpy arrays into ``libcm_oracle.so``
+(built from ``cm_oracle.c``).  The arithmetic lives in the C file.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class Oracle:
+    """ctypes handle on one build of the oracle library."""
+
+    def __init__(self, path: str):
+        L = ctypes.CDLL(path)
+        L.cmo_n_params.restype = ctypes.c_int32
+        L.cmo_eval.restype = None
+        L.cmo_eval.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, _f32p, _f32p,
+                               _f32p, _f64p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_int32]
+        L.cmo_select.restype = ctypes.c_int32
+        L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
+        self.L = L
+        self.path = path
+
+    def n_params(self) -> int:
+        return int(self.L.cmo_n_params())
+
+    def eval_query(self, params, pipe, sched, terms, *, nthreads: int = 0,
+                   stage_costs: bool = False, coefs: bool = False):
+        """FP64 predicted runtime per candidate of one query.
+
+        pipe[S][56], sched[S][N][40], terms[S][N][8] (float32 values).  Returns
+        cost[N] (float64), plus stage_cost[S][N] and coef[S][N][8] when asked.
+        """
+        params, pipe, sched, terms = _f32(params), _f32(pipe), _f32(sched), _f32(terms)
+        S, N = sched.shape[0], sched.shape[1]
+        assert params.size == self.n_params()
+        assert pipe.shape == (S, 56) and sched.shape == (S, N, 40)
+        assert terms.shape == (S, N, 8)
+        cost = np.empty(N, np.float64)
+        sc = np.empty((S, N), np.float64) if stage_costs else None
+        co = np.empty((S, N, 8), np.float64) if coefs else None
+        self.L.cmo_eval(params, S, N, pipe, sched, terms, cost,
+                        None if sc is None else sc.ctypes.data,
+                        None if co is None else co.ctypes.data, int(nthreads))
+        out = [cost]
+        if stage_costs:
+            out.append(sc)
+        if coefs:
+            out.append(co)
+        return out[0] if len(out) == 1 else tuple(out)
+
+    def select(self, cost, k: int):
+        """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""
+        cost = np.ascontiguousarray(cost, dtype=np.float64)
+        idx = np.empty(k, np.int32)
+        val = np.empty(k, np.float64)
+        rc = self.L.cmo_select(cost, cost.size, int(k), idx, val)
+        if rc != 0:
+            raise ValueError(f"cmo_select failed ({rc})")
+        return idx, val
+
+
+_DEFAULT = None
+
+
+def lib() -> Oracle:
+    """The default oracle build, compiled first only if it is missing."""
+    global _DEFAULT
+    if _DEFAULT is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _DEFAULT = Oracle(_build.LIB)
+    return _DEFAULT
+
+
+def n_params() -> int:
+    return lib().n_params()
+
+
+def eval_query(*a, **kw):
+    return lib().eval_query(*a, **kw)
+
+
+def select(cost, k: int):
+    return lib().select(cost, k)

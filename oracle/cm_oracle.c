@@ -1,0 +1,181 @@
+/*
+ * cm_oracle.c -- plain FP64 CPU oracle of the learned cost model and of beam
+ * selection, from Anderson et al., "Efficient Automatic Scheduling of Imaging
+ * and Vision Pipelines for the GPU" (OOPSLA 2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * definition that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never calls it and shares no code, header or table with it.
+ *
+ * Everything is computed in double precision from float32 inputs widened
+ * exactly, with scalar loops in the order the paper states the model
+ * (Sec. 5.2): log transform of the features, two fully connected embeddings,
+ * the embeddings stacked, a fully connected layer, a second one giving
+ * non-negative coefficients, the coefficients applied to the hand-derived
+ * per-stage cost terms (App. B: every cost component is linear in the learned
+ * coefficients), and the per-stage predictions summed over all stages.
+ * Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math).
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *  - both feature groups are log-transformed with log1p (operation counts can
+ *    be zero);
+ *  - there is no activation after the embeddings;
+ *  - "positive weights" are produced by a ReLU, so exact zeros are allowed;
+ *  - every layer has a bias;
+ *  - the algorithm-specific features are one vector per (query, stage),
+ *    shared by all candidates of the query;
+ *  - the best candidate is the one with the lowest predicted runtime; ties go
+ *    to the lower candidate index; -0 equals +0; NaN ranks after +inf.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "cm_oracle.h"
+
+/* Parameter blob layout: W_p[24][56] b_p[24] W_s[24][40] b_s[24]
+ * W_1[32][48] b_1[32] W_2[8][32] b_2[8]; matrices are [out][in]. */
+#define FP 56
+#define FS 40
+#define E 24
+#define H 32
+#define C 8
+
+typedef struct {
+    const float *Wp, *bp, *Ws, *bs, *W1, *b1, *W2, *b2;
+} cmo_params;
+
+static cmo_params split_params(const float *blob)
+{
+    cmo_params p;
+    const float *q = blob;
+    p.Wp = q; q += E * FP;
+    p.bp = q; q += E;
+    p.Ws = q; q += E * FS;
+    p.bs = q; q += E;
+    p.W1 = q; q += H * 2 * E;
+    p.b1 = q; q += H;
+    p.W2 = q; q += C * H;
+    p.b2 = q; q += C;
+    return p;
+}
+
+int32_t cmo_n_params(void) { return E * FP + E + E * FS + E + H * 2 * E + H + C * H + C; }
+
+/* One (candidate, stage) evaluation, Sec. 5.2: coefficients c[8] and the
+ * stage's predicted cost sum_j c_j * t_j. */
+static double stage_eval(const cmo_params *P, const float *pipe_s,
+                         const float *sched_si, const float *terms_si,
+                         double *coef_out)
+{
+    double p[FP], x[FS], z[2 * E], h[H], c[C];
+    /* log transform of both feature groups */
+    for (int f = 0; f < FP; ++f) p[f] = log1p((double)pipe_s[f]);
+    for (int f = 0; f < FS; ++f) x[f] = log1p((double)sched_si[f]);
+    /* two embeddings, stacked: algorithm embedding first */
+    for (int e = 0; e < E; ++e) {
+        double a = (double)P->bp[e];
+        for (int f = 0; f < FP; ++f) a += (double)P->Wp[e * FP + f] * p[f];
+        z[e] = a;
+    }
+    for (int e = 0; e < E; ++e) {
+        double a = (double)P->bs[e];
+        for (int f = 0; f < FS; ++f) a += (double)P->Ws[e * FS + f] * x[f];
+        z[E + e] = a;
+    }
+    /* fully connected layer with ReLU */
+    for (int j = 0; j < H; ++j) {
+        double a = (double)P->b1[j];
+        for (int k = 0; k < 2 * E; ++k) a += (double)P->W1[j * 2 * E + k] * z[k];
+        h[j] = a > 0.0 ? a : 0.0;
+    }
+    /* output layer with ReLU: the non-negative coefficients */
+    for (int m = 0; m < C; ++m) {
+        double a = (double)P->b2[m];
+        for (int j = 0; j < H; ++j) a += (double)P->W2[m * H + j] * h[j];
+        c[m] = a > 0.0 ? a : 0.0;
+    }
+    /* coefficients weight the hand-derived cost terms (App. B) */
+    double v = 0.0;
+    for (int m = 0; m < C; ++m) v += c[m] * (double)terms_si[m];
+    if (coef_out)
+        for (int m = 0; m < C; ++m) coef_out[m] = c[m];
+    return v;
+}
+
+void cmo_eval(const float *params, int32_t S, int32_t N, const float *pipe,
+              const float *sched, const float *terms, double *cost_out,
+              double *stage_cost_out, double *coef_out, int32_t nthreads)
+{
+    cmo_params P = split_params(params);
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int64_t i = 0; i < (int64_t)N; ++i) {
+        /* per-stage predictions summed over all stages, ascending stage order */
+        double total = 0.0;
+        for (int64_t s = 0; s < (int64_t)S; ++s) {
+            const int64_t row = s * (int64_t)N + i;
+            double *co = coef_out ? coef_out + row * C : NULL;
+            double v = stage_eval(&P, pipe + s * FP, sched + row * FS,
+                                  terms + row * C, co);
+            if (stage_cost_out) stage_cost_out[row] = v;
+            total += v;
+        }
+        cost_out[i] = total;
+    }
+    (void)nthreads;
+}
+
+/* ---- beam selection: the k best states of a priority queue (Sec. 4) ---- */
+
+typedef struct {
+    double key;
+    int32_t idx;
+    int32_t nan;
+} cmo_item;
+
+/* Total order: lower predicted cost first, NaN after every number, -0 == +0
+ * (numeric comparison), equal costs by ascending candidate index.  With the
+ * index as the last key this is exactly the order a stable sort produces. */
+static int item_cmp(const void *a, const void *b)
+{
+    const cmo_item *A = (const cmo_item *)a, *B = (const cmo_item *)b;
+    if (A->nan != B->nan) return A->nan - B->nan;
+    if (!A->nan) {
+        if (A->key < B->key) return -1;
+        if (A->key > B->key) return 1;
+    }
+    return (A->idx > B->idx) - (A->idx < B->idx);
+}
+
+int32_t cmo_select(const double *cost, int32_t N, int32_t k, int32_t *idx_out,
+                   double *val_out)
+{
+    if (N < 0 || k < 0) return -1;
+    cmo_item *it = (cmo_item *)malloc(sizeof(cmo_item) * (size_t)(N > 0 ? N : 1));
+    if (!it) return -2;
+    for (int32_t i = 0; i < N; ++i) {
+        it[i].key = cost[i];
+        it[i].idx = i;
+        it[i].nan = isnan(cost[i]) ? 1 : 0;
+    }
+    qsort(it, (size_t)N, sizeof(cmo_item), item_cmp);
+    for (int32_t j = 0; j < k; ++j) {
+        if (j < N) {
+            idx_out[j] = it[j].idx;
+            val_out[j] = it[j].key;
+        } else { /* fewer candidates than beam slots: padding */
+            idx_out[j] = -1;
+            val_out[j] = INFINITY;
+        }
+    }
+    free(it);
+    return 0;
+}

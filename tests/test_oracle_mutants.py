@@ -1,0 +1,90 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's C source (on the CPU,
+in a temporary directory), builds it, and runs the pin tests against it: at
+least one pin must fail.  The unmodified source must pass them all.
+"""
+import os
+
+import pytest
+
+import oracle
+from oracle import build as obuild
+from tests import test_oracle_pins as pins
+
+PIN_TESTS = [
+    pins.test_hand_examples,
+    pins.test_hand_example_coefficients,
+    lambda o: pins.test_log_transform_closed_form(o, 0),
+    lambda o: pins.test_log_transform_closed_form(o, 1),
+    pins.test_log1p_matches_math_over_range,
+    pins.test_stage_permutation_invariance,
+    pins.test_coefficients_nonnegative,
+    pins.test_split_stages_sum,
+    pins.test_candidate_permutation,
+    pins.test_unit_coefficients_reduce_to_fsum,
+    pins.test_constant_embeddings,
+    pins.test_positive_model_is_a_matmul_chain,
+    pins.test_select_all_equal,
+    pins.test_select_signed_zero_tie,
+    pins.test_select_nan_last_and_padding,
+    pins.test_select_brute_force_tiny,
+]
+
+# (name, text in cm_oracle.c, replacement)
+MUTANTS = [
+    ("stack order swapped", "z[E + e] = a;", "z[e] = a; z[E + e] = z[E + e];"),
+    ("no hidden ReLU", "h[j] = a > 0.0 ? a : 0.0;", "h[j] = a;"),
+    ("no output ReLU", "c[m] = a > 0.0 ? a : 0.0;", "c[m] = a;"),
+    ("log instead of log1p", "x[f] = log1p((double)sched_si[f]);",
+     "x[f] = log((double)sched_si[f] + 1e-300);"),
+    ("pipeline features not logged", "p[f] = log1p((double)pipe_s[f]);",
+     "p[f] = (double)pipe_s[f];"),
+    ("W_1 transposed", "P->W1[j * 2 * E + k]", "P->W1[(k % H) * 2 * E + (j + k / H * H) % (2 * E)]"),
+    ("W_s transposed", "P->Ws[e * FS + f]", "P->Ws[(f % E) * FS + (e + f / E * E) % FS]"),
+    ("b_s dropped", "double a = (double)P->bs[e];", "double a = 0.0;"),
+    ("b_1 dropped", "double a = (double)P->b1[j];", "double a = 0.0;"),
+    ("b_2 dropped", "double a = (double)P->b2[m];", "double a = 0.0;"),
+    ("terms shifted", "c[m] * (double)terms_si[m]", "c[m] * (double)terms_si[(m + 1) % C]"),
+    ("last stage only", "total += v;", "total = v;"),
+    ("ties to higher index", "return (A->idx > B->idx) - (A->idx < B->idx);",
+     "return (A->idx < B->idx) - (A->idx > B->idx);"),
+    ("NaN first", "return A->nan - B->nan;", "return B->nan - A->nan;"),
+    ("padding index 0", "idx_out[j] = -1;", "idx_out[j] = 0;"),
+    ("descending order", "if (A->key < B->key) return -1;", "if (A->key > B->key) return -1;"),
+]
+
+
+def _failures(orc):
+    failed = 0
+    for t in PIN_TESTS:
+        try:
+            t(orc)
+        except (AssertionError, ValueError):
+            failed += 1
+    return failed
+
+
+def _build_variant(tmp_path, name, src_text):
+    d = tmp_path / name.replace(" ", "_")
+    d.mkdir()
+    src = d / "cm_oracle.c"
+    src.write_text(src_text)
+    out = str(d / "libcm_oracle_variant.so")
+    obuild.compile_lib(str(src), out)
+    return oracle.Oracle(out)
+
+
+def test_unmodified_source_passes(tmp_path):
+    with open(obuild.SRC) as f:
+        text = f.read()
+    assert _failures(_build_variant(tmp_path, "clean", text)) == 0
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new):
+    with open(obuild.SRC) as f:
+        text = f.read()
+    assert text.count(old) == 1, f"mutation site not unique: {old!r}"
+    orc = _build_variant(tmp_path, name, text.replace(old, new))
+    assert _failures(orc) > 0, f"no pin caught mutant: {name}"
