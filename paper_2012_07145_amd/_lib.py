@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/cm.h (libcm.so).
+
+Names and argument order follow the header; this module only marshals
+arguments.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcm.so")
+
+CM_OK, CM_EINVAL, CM_ENOMEM, CM_EDEVICE, CM_EAGAIN, CM_E2BIG = 0, -1, -2, -3, -4, -5
+CM_ENOTFOUND, CM_ECANCELED, CM_EUNSUPPORTED = -6, -7, -8
+STATUS_NAMES = {0: "CM_OK", -1: "CM_EINVAL", -2: "CM_ENOMEM", -3: "CM_EDEVICE",
+                -4: "CM_EAGAIN", -5: "CM_E2BIG", -6: "CM_ENOTFOUND", -7: "CM_ECANCELED",
+                -8: "CM_EUNSUPPORTED"}
+CM_FP32, CM_BF16 = 0, 1
+CM_MAX_K = 256
+CM_N_PARAMS = 4184
+CM_STAGE_CHUNK = 16
+
+# Every function the header declares, for the export check.
+EXPORTS = (
+    "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
+    "cm_eval_batch", "cm_topk_per_query", "cm_last_error", "cm_version",
+)
+
+
+class cm_model_desc(ctypes.Structure):
+    _fields_ = [("n_pipe_features", ctypes.c_int32), ("n_sched_features", ctypes.c_int32),
+                ("embed", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("n_coefs", ctypes.c_int32)]
+
+
+class cm_workspace_desc(ctypes.Structure):
+    _fields_ = [("max_queries", ctypes.c_int32), ("max_stages", ctypes.c_int64),
+                ("max_cands", ctypes.c_int64), ("max_rows", ctypes.c_int64),
+                ("max_k", ctypes.c_int32)]
+
+
+class cm_query(ctypes.Structure):
+    _fields_ = [("n_stages", ctypes.c_int32), ("n_cands", ctypes.c_int32),
+                ("pipe_off", ctypes.c_int64), ("sched_off", ctypes.c_int64),
+                ("terms_off", ctypes.c_int64), ("cost_off", ctypes.c_int64)]
+
+
+class cm_batch(ctypes.Structure):
+    _fields_ = [("n_queries", ctypes.c_int32), ("queries", ctypes.POINTER(cm_query)),
+                ("pipe", ctypes.c_void_p), ("sched", ctypes.c_void_p),
+                ("terms", ctypes.c_void_p)]
+
+
+class CmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_L = None
+
+
+def lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.cm_model_create.argtypes = [ctypes.POINTER(cm_model_desc), vp, ctypes.POINTER(vp)]
+        L.cm_model_destroy.argtypes = [vp]
+        L.cm_workspace_create.argtypes = [ctypes.POINTER(cm_workspace_desc), ctypes.POINTER(vp)]
+        L.cm_workspace_destroy.argtypes = [vp]
+        L.cm_eval_batch.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp, vp]
+        L.cm_topk_per_query.argtypes = [vp, ctypes.POINTER(cm_batch), i32, vp, vp, vp, vp]
+        for f in ("cm_model_create", "cm_model_destroy", "cm_workspace_create",
+                  "cm_workspace_destroy", "cm_eval_batch", "cm_topk_per_query"):
+            getattr(L, f).restype = i32
+        L.cm_last_error.restype = ctypes.c_char_p
+        L.cm_last_error.argtypes = []
+        L.cm_version.restype = i32
+        L.cm_version.argtypes = []
+        _L = L
+        del i64
+    return _L
+
+
+def check(status: int):
+    if status != CM_OK:
+        raise CmError(status, lib().cm_last_error().decode())
+    return status

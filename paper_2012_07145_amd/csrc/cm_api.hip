@@ -1,0 +1,411 @@
+// cm_api.hip -- the C ABI (include/cm.h): argument validation, model weight
+// packing, workspace allocation and kernel dispatch.  No device work is
+// queued before every argument has been checked.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "cm_internal.h"
+
+struct cm_model {
+    cm::Model m;
+};
+struct cm_workspace {
+    cm::Workspace w;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+cm_status fail(cm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define CM_HIP(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(CM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+uint16_t f32_to_bf16(float f)  // round to nearest even
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_to_f32(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// hi + lo bf16 pair of a double value
+void split_bf16(double w, uint16_t &hi, uint16_t &lo)
+{
+    hi = f32_to_bf16((float)w);
+    lo = f32_to_bf16((float)(w - (double)bf16_to_f32(hi)));
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <class T>
+cm_status dev_alloc(T **p, size_t count, const char *what)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(CM_ENOMEM, "device allocation of %s (%zu bytes) failed", what,
+                    count * sizeof(T));
+    }
+    return CM_OK;
+}
+
+void free_model(cm::Model &m)
+{
+    if (m.d_params) (void)hipFree(m.d_params);
+    if (m.d_beta) (void)hipFree(m.d_beta);
+    if (m.d_bf16) (void)hipFree(m.d_bf16);
+    m = cm::Model{};
+}
+
+void free_ws(cm::Workspace &w)
+{
+    if (w.d_U) (void)hipFree(w.d_U);
+    if (w.d_part) (void)hipFree(w.d_part);
+    if (w.d_ecnt) (void)hipFree(w.d_ecnt);
+    if (w.d_tpart) (void)hipFree(w.d_tpart);
+    if (w.d_tcnt) (void)hipFree(w.d_tcnt);
+    w = cm::Workspace{};
+}
+
+cm_status check_device(int want)
+{
+    int dev = -1;
+    CM_HIP(hipGetDevice(&dev));
+    if (dev != want)
+        return fail(CM_EINVAL, "object lives on device %d but device %d is current", want, dev);
+    return CM_OK;
+}
+
+// Validate a batch against a workspace.  Fills the totals.
+cm_status check_batch(const cm_batch *b, const cm::Workspace &w, cm_precision prec, bool eval)
+{
+    if (!b) return fail(CM_EINVAL, "batch is NULL");
+    if (b->n_queries < 0) return fail(CM_EINVAL, "n_queries < 0");
+    if (b->n_queries > 0 && !b->queries) return fail(CM_EINVAL, "queries is NULL");
+    if (b->n_queries > w.cap.max_queries)
+        return fail(CM_E2BIG, "batch has %d queries, workspace holds %d", b->n_queries,
+                    w.cap.max_queries);
+    int64_t stages = 0, cands = 0, rows = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) {
+        const cm_query &Q = b->queries[q];
+        if (Q.n_stages < 1) return fail(CM_EINVAL, "query %d: n_stages %d < 1", q, Q.n_stages);
+        if (Q.n_cands < 0) return fail(CM_EINVAL, "query %d: n_cands %d < 0", q, Q.n_cands);
+        if (Q.pipe_off < 0 || Q.sched_off < 0 || Q.terms_off < 0 || Q.cost_off < 0)
+            return fail(CM_EINVAL, "query %d: negative offset", q);
+        if (eval && (Q.sched_off % 8) != 0)
+            return fail(CM_EINVAL, "query %d: sched_off %lld is not a multiple of 8", q,
+                        (long long)Q.sched_off);
+        if (eval && (Q.terms_off % 4) != 0)
+            return fail(CM_EINVAL, "query %d: terms_off %lld is not a multiple of 4", q,
+                        (long long)Q.terms_off);
+        stages += Q.n_stages;
+        cands += Q.n_cands;
+        rows += (int64_t)Q.n_stages * Q.n_cands;
+    }
+    if (eval) {
+        if (stages > w.cap.max_stages)
+            return fail(CM_E2BIG, "batch has %lld stages, workspace holds %lld",
+                        (long long)stages, (long long)w.cap.max_stages);
+        if (rows > w.cap.max_rows)
+            return fail(CM_E2BIG, "batch has %lld rows, workspace holds %lld", (long long)rows,
+                        (long long)w.cap.max_rows);
+    }
+    if (cands > w.cap.max_cands)
+        return fail(CM_E2BIG, "batch has %lld candidates, workspace holds %lld",
+                    (long long)cands, (long long)w.cap.max_cands);
+    if (eval && cands > 0) {
+        if (!b->pipe || !b->sched || !b->terms)
+            return fail(CM_EINVAL, "batch pipe/sched/terms pointer is NULL");
+        if (!aligned(b->sched, 16) || !aligned(b->terms, 16) || !aligned(b->pipe, 4))
+            return fail(CM_EINVAL, "sched and terms must be 16-byte aligned");
+    }
+    (void)prec;
+    return CM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cm_last_error(void) { return g_err.c_str(); }
+
+int32_t cm_version(void) { return (CM_VERSION_MAJOR << 16) | CM_VERSION_MINOR; }
+
+cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model **out)
+{
+    using namespace cm;
+    if (!d || !params || !out) return fail(CM_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (d->n_pipe_features != FP || d->n_sched_features != FS || d->embed != E ||
+        d->hidden != H || d->n_coefs != C)
+        return fail(CM_EINVAL, "model dimensions must be 56/40/24/32/8");
+    for (int i = 0; i < N_PARAMS; ++i)
+        if (!std::isfinite(params[i])) return fail(CM_EINVAL, "parameter %d is not finite", i);
+
+    cm_model *M = new (std::nothrow) cm_model;
+    if (!M) return fail(CM_ENOMEM, "host allocation failed");
+    Model &m = M->m;
+    if (hipGetDevice(&m.device) != hipSuccess) {
+        delete M;
+        return fail(CM_EDEVICE, "no HIP device");
+    }
+
+    // W_1[:, 24:] b_s, and the folded schedule layer Wf = W_1[:, 24:] W_s,
+    // scaled by ln 2 because the evaluator feeds log2(1 + x).
+    const float *Ws = params + OFF_WS, *bs = params + OFF_BS;
+    const float *W1 = params + OFF_W1, *W2 = params + OFF_W2;
+    float beta[H];
+    double Wf[H][FS];
+    for (int j = 0; j < H; ++j) {
+        double b = 0.0;
+        for (int e = 0; e < E; ++e) b += (double)W1[j * 2 * E + E + e] * (double)bs[e];
+        beta[j] = (float)b;
+        for (int f = 0; f < FS; ++f) {
+            double a = 0.0;
+            for (int e = 0; e < E; ++e) a += (double)W1[j * 2 * E + E + e] * (double)Ws[e * FS + f];
+            Wf[j][f] = a * 0.69314718055994530942;
+        }
+    }
+    Bf16Pack pk;
+    std::memset(&pk, 0, sizeof pk);
+    for (int st = 0; st < 3; ++st)
+        for (int lane = 0; lane < 64; ++lane) {
+            uint16_t hi[8], lo[8];
+            for (int j = 0; j < 8; ++j) {
+                const int mrow = lane & 31, k = st * 16 + (lane >> 5) * 8 + j;
+                split_bf16(k < FS ? Wf[mrow][k] : 0.0, hi[j], lo[j]);
+            }
+            std::memcpy(&pk.a1[0][st][lane], hi, 16);
+            std::memcpy(&pk.a1[1][st][lane], lo, 16);
+        }
+    for (int t = 0; t < 2; ++t)
+        for (int lane = 0; lane < 64; ++lane) {
+            uint16_t hi[8], lo[8];
+            const int mo = lane & 31, hf = lane >> 5;
+            for (int j = 0; j < 8; ++j) {
+                const int r = t * 8 + j;                      // output register of layer 1
+                const int p = (r >> 2) * 8 + hf * 4 + (r & 3);  // its hidden unit
+                split_bf16(mo < C ? (double)W2[mo * H + p] : 0.0, hi[j], lo[j]);
+            }
+            std::memcpy(&pk.a2[0][t][lane], hi, 16);
+            std::memcpy(&pk.a2[1][t][lane], lo, 16);
+        }
+    for (int mo = 0; mo < C; ++mo) pk.b2[mo] = params[OFF_B2 + mo];
+
+    cm_status st;
+    if ((st = dev_alloc(&m.d_params, N_PARAMS, "parameters")) != CM_OK ||
+        (st = dev_alloc(&m.d_beta, H, "beta")) != CM_OK ||
+        (st = dev_alloc(&m.d_bf16, 1, "bf16 operands")) != CM_OK) {
+        free_model(m);
+        delete M;
+        return st;
+    }
+    if (hipMemcpy(m.d_params, params, N_PARAMS * sizeof(float), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(m.d_beta, beta, sizeof beta, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m.d_bf16, &pk, sizeof pk, hipMemcpyHostToDevice) != hipSuccess) {
+        free_model(m);
+        delete M;
+        return fail(CM_EDEVICE, "copy of model parameters failed");
+    }
+    *out = M;
+    return CM_OK;
+}
+
+cm_status cm_model_destroy(cm_model *M)
+{
+    if (!M) return fail(CM_EINVAL, "model is NULL");
+    free_model(M->m);
+    delete M;
+    return CM_OK;
+}
+
+cm_status cm_workspace_create(const cm_workspace_desc *d, cm_workspace **out)
+{
+    using namespace cm;
+    if (!d || !out) return fail(CM_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (d->max_queries < 1 || d->max_stages < 1 || d->max_cands < 0 || d->max_rows < 0 ||
+        d->max_k < 1 || d->max_k > CM_MAX_K)
+        return fail(CM_EINVAL, "bad workspace capacities");
+    if (d->max_rows > ((int64_t)1 << 40) || d->max_cands > INT32_MAX ||
+        d->max_stages > INT32_MAX / 2)
+        return fail(CM_EINVAL, "workspace capacities too large");
+    cm_workspace *W = new (std::nothrow) cm_workspace;
+    if (!W) return fail(CM_ENOMEM, "host allocation failed");
+    Workspace &w = W->w;
+    w.cap = *d;
+    if (hipGetDevice(&w.device) != hipSuccess) {
+        delete W;
+        return fail(CM_EDEVICE, "no HIP device");
+    }
+    w.part_cap = d->max_rows / SCHUNK + d->max_cands + 1;
+    w.ecnt_cap = d->max_cands / TILE_ROWS + d->max_queries + 1;
+    w.tpart_cap = (d->max_cands / TOPK_TILE + d->max_queries + 1) * (int64_t)d->max_k;
+    cm_status st;
+    if ((st = dev_alloc(&w.d_U, (size_t)d->max_stages * H, "hoisted stage vectors")) != CM_OK ||
+        (st = dev_alloc(&w.d_part, (size_t)w.part_cap, "partial sums")) != CM_OK ||
+        (st = dev_alloc(&w.d_ecnt, (size_t)w.ecnt_cap, "eval counters")) != CM_OK ||
+        (st = dev_alloc(&w.d_tpart, (size_t)w.tpart_cap, "beam lists")) != CM_OK ||
+        (st = dev_alloc(&w.d_tcnt, (size_t)QMAX, "beam counters")) != CM_OK) {
+        free_ws(w);
+        delete W;
+        return st;
+    }
+    if (hipMemset(w.d_ecnt, 0, w.ecnt_cap * sizeof(int32_t)) != hipSuccess ||
+        hipMemset(w.d_tcnt, 0, QMAX * sizeof(int32_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        free_ws(w);
+        delete W;
+        return fail(CM_EDEVICE, "workspace initialisation failed");
+    }
+    *out = W;
+    return CM_OK;
+}
+
+cm_status cm_workspace_destroy(cm_workspace *W)
+{
+    if (!W) return fail(CM_EINVAL, "workspace is NULL");
+    free_ws(W->w);
+    delete W;
+    return CM_OK;
+}
+
+cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
+                        cm_workspace *W, float *cost_out, cm_stream stream)
+{
+    using namespace cm;
+    if (!M || !W) return fail(CM_EINVAL, "model or workspace is NULL");
+    if (prec != CM_FP32 && prec != CM_BF16)
+        return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
+    cm_status st = check_batch(b, W->w, prec, true);
+    if (st != CM_OK) return st;
+    if ((st = check_device(M->m.device)) != CM_OK) return st;
+    if (W->w.device != M->m.device) return fail(CM_EINVAL, "model and workspace devices differ");
+    int64_t cands = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) cands += b->queries[q].n_cands;
+    if (cands == 0) return CM_OK;
+    if (!cost_out) return fail(CM_EINVAL, "cost_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const Workspace &w = W->w;
+
+    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
+        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
+        EvalLaunch L;
+        std::memset(&L, 0, sizeof L);
+        L.nq = ng;
+        int64_t stage = 0, task = 0, cnt = 0, part = 0;
+        for (int32_t j = 0; j < ng; ++j) {
+            const cm_query &Q = b->queries[g0 + j];
+            EvalQ &e = L.q[j];
+            e.S = Q.n_stages;
+            e.N = Q.n_cands;
+            e.pipe_off = Q.pipe_off;
+            e.sched_off = Q.sched_off;
+            e.terms_off = Q.terms_off;
+            e.cost_off = Q.cost_off;
+            e.stage0 = (int32_t)stage;
+            e.task0 = (int32_t)task;
+            e.cnt0 = (int32_t)cnt;
+            e.nchunk = (int32_t)cdiv(Q.n_stages, SCHUNK);
+            e.part0 = part;
+            stage += Q.n_stages;
+            if (prec == CM_FP32) {
+                task += cdiv(Q.n_cands, 64);
+            } else {
+                const int64_t tiles = cdiv(Q.n_cands, TILE_ROWS);
+                task += tiles * e.nchunk;
+                cnt += tiles;
+                if (e.nchunk > 1) part += (int64_t)e.nchunk * Q.n_cands;
+            }
+        }
+        if (task > INT32_MAX || part > w.part_cap || cnt > w.ecnt_cap)
+            return fail(CM_E2BIG, "batch exceeds workspace scratch");
+        L.ntasks = (int32_t)task;
+        L.nstages = (int32_t)stage;
+        CM_HIP(launch_hoist(L, M->m, prec != CM_FP32, b->pipe, w.d_U, s));
+        if (prec == CM_FP32)
+            CM_HIP(launch_eval_fp32(L, M->m, (const float *)b->sched, b->terms, w.d_U, cost_out,
+                                    s));
+        else
+            CM_HIP(launch_eval_bf16(L, M->m, (const uint16_t *)b->sched, b->terms, w.d_U,
+                                    w.d_part, w.d_ecnt, cost_out, s));
+    }
+    return CM_OK;
+}
+
+cm_status cm_topk_per_query(const float *cost, const cm_batch *b, int32_t k, cm_workspace *W,
+                            int32_t *idx_out, float *val_out, cm_stream stream)
+{
+    using namespace cm;
+    if (!W) return fail(CM_EINVAL, "workspace is NULL");
+    if (k < 1 || k > CM_MAX_K || k > W->w.cap.max_k)
+        return fail(CM_EINVAL, "k=%d outside [1, %d]", k, std::min(CM_MAX_K, W->w.cap.max_k));
+    cm_status st = check_batch(b, W->w, CM_FP32, false);
+    if (st != CM_OK) return st;
+    if ((st = check_device(W->w.device)) != CM_OK) return st;
+    if (b->n_queries == 0) return CM_OK;
+    if (!idx_out || !val_out) return fail(CM_EINVAL, "idx_out or val_out is NULL");
+    int64_t cands = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) cands += b->queries[q].n_cands;
+    if (cands > 0 && !cost) return fail(CM_EINVAL, "cost is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const Workspace &w = W->w;
+
+    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
+        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
+        TopkLaunch L;
+        std::memset(&L, 0, sizeof L);
+        L.nq = ng;
+        L.k = k;
+        int64_t tile = 0;
+        for (int32_t j = 0; j < ng; ++j) {
+            const cm_query &Q = b->queries[g0 + j];
+            TopkQ &t = L.q[j];
+            t.N = Q.n_cands;
+            t.out_q = g0 + j;
+            t.cost_off = Q.cost_off;
+            t.tile0 = (int32_t)tile;
+            t.ntiles = (int32_t)std::max<int64_t>(1, cdiv(Q.n_cands, TOPK_TILE));
+            tile += t.ntiles;
+        }
+        if (tile * k > w.tpart_cap) return fail(CM_E2BIG, "batch exceeds workspace beam lists");
+        L.ntasks = (int32_t)tile;
+        CM_HIP(launch_topk(L, cost, w.d_tpart, w.d_tcnt, idx_out, val_out, s));
+    }
+    return CM_OK;
+}
+
+}  // extern "C"
