@@ -49,7 +49,7 @@ extern "C" {
 #define CM_N_COEFS 8
 #define CM_N_PARAMS 4184     /* float32 parameters, layout in cm_model_create */
 #define CM_MAX_K 256         /* largest beam width of cm_topk_per_query */
-#define CM_STAGE_CHUNK 16    /* stages per partial Kahan sum (reduced precisions) */
+#define CM_STAGE_CHUNK 16    /* sets the stage split of CM_BF16 (see cm_eval_batch) */
 
 typedef int32_t cm_status;
 enum {
@@ -153,11 +153,14 @@ typedef struct {
  *   cost[i] = sum over stages s of  sum_j c_j(s, i) * terms[s][i][j],
  *   c(s, i) = ReLU(W_2 ReLU(W_1 [W_p log1p(pipe[s]) + b_p ;
  *                                W_s log1p(sched[s][i]) + b_s] + b_1) + b_2).
- * The stage sum is Kahan-compensated float32 in ascending stage order; in
- * CM_BF16 it runs over chunks of CM_STAGE_CHUNK stages whose compensated
- * partial sums are then combined in ascending chunk order.  Every candidate's
- * result depends only on its own query's data: the same query gives
- * bit-identical costs alone or inside any batch.
+ * The stage sum is Kahan-compensated float32 in ascending stage order.  In
+ * CM_BF16 the stages are first split into P contiguous near-equal parts
+ * (P = 1 for n_stages <= CM_STAGE_CHUNK/2, 2 for <= CM_STAGE_CHUNK, 4 for
+ * <= 2*CM_STAGE_CHUNK, else 8),
+ * each summed with compensation, and the parts' (sum, compensation) pairs are
+ * combined in ascending order.  Every candidate's result depends only on its
+ * own query's data: the same query gives bit-identical costs alone or inside
+ * any batch.
  * cost_out is a device pointer; results land at cost_out[cost_off + i].
  * Asynchronous on `stream`; allocates nothing.
  * Errors: CM_EINVAL (bad descriptor, misaligned offset, NULL pointer),
@@ -166,6 +169,28 @@ typedef struct {
 cm_status cm_eval_batch(const cm_model *model, cm_precision precision,
                         const cm_batch *batch, cm_workspace *ws, float *cost_out,
                         cm_stream stream);
+
+/* Per-stage hoist (Sec. 5.2): the algorithm features of a stage are shared by
+ * every candidate of its query, so their share of the first layer is
+ * computed once per stage:
+ *   U[row][j] = b_1[j] + sum_e W_1[j][e] (W_p log1p(pipe[s]) + b_p)[e]
+ * (for CM_BF16 also + sum_e W_1[j][24 + e] b_s[e], since that form folds the
+ * schedule embedding into the first layer).  Rows are written in batch order:
+ * query q's stage s goes to row (n_stages of queries 0..q-1) + s, 32 floats
+ * per row, into U_out (device, 16-byte aligned, at least sum(n_stages) * 32
+ * floats).  Only n_stages, pipe_off and pipe are read.  Asynchronous on
+ * `stream`; allocates nothing.  Errors: CM_EINVAL, CM_EUNSUPPORTED,
+ * CM_EDEVICE. */
+cm_status cm_hoist_stages(const cm_model *model, cm_precision precision,
+                          const cm_batch *batch, float *U_out, cm_stream stream);
+
+/* cm_eval_batch without the hoist: reads the per-stage rows U (device, laid
+ * out as cm_hoist_stages writes them for the same precision and batch order)
+ * instead of computing them; one kernel launch per 32 queries.  Same results,
+ * errors and asynchrony as cm_eval_batch. */
+cm_status cm_eval_hoisted(const cm_model *model, cm_precision precision,
+                          const cm_batch *batch, const float *U, cm_workspace *ws,
+                          float *cost_out, cm_stream stream);
 
 /* Beam selection (Sec. 4): for every query q, the k candidates with the
  * lowest predicted runtime, ascending; equal costs are ranked by the lower

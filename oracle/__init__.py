@@ -31,6 +31,7 @@ class Oracle:
     def __init__(self, path: str):
         L = ctypes.CDLL(path)
         L.cmo_n_params.restype = ctypes.c_int32
+        L.cmo_max_threads.restype = ctypes.c_int32
         L.cmo_eval.restype = None
         L.cmo_eval.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, _f32p, _f32p,
                                _f32p, _f64p, ctypes.c_void_p, ctypes.c_void_p,
@@ -39,6 +40,9 @@ class Oracle:
         L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
         self.L = L
         self.path = path
+
+    def max_threads(self) -> int:
+        return int(self.L.cmo_max_threads())
 
     def n_params(self) -> int:
         return int(self.L.cmo_n_params())

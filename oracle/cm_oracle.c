@@ -65,6 +65,15 @@ static cmo_params split_params(const float *blob)
     return p;
 }
 
+int32_t cmo_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int32_t cmo_n_params(void) { return E * FP + E + E * FS + E + H * 2 * E + H + C * H + C; }
 
 /* One (candidate, stage) evaluation, Sec. 5.2: coefficients c[8] and the

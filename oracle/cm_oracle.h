@@ -12,6 +12,9 @@
 extern "C" {
 #endif
 
+/* Threads an nthreads <= 0 call uses (OpenMP's maximum). */
+int32_t cmo_max_threads(void);
+
 /* Length of the float32 parameter blob (4184). */
 int32_t cmo_n_params(void);
 

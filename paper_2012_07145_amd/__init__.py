@@ -18,7 +18,8 @@ from ._lib import (CM_BF16, CM_FP32, CM_MAX_K, CM_N_PARAMS, CM_STAGE_CHUNK,  # n
 __all__ = [
     "CM_FP32", "CM_BF16", "CM_MAX_K", "CmError", "Model", "Workspace", "Batch",
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
-    "cm_eval_batch", "cm_topk_per_query", "cm_version", "pack_queries",
+    "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
+    "cm_version", "pack_queries",
 ]
 
 PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16}
@@ -139,6 +140,22 @@ def cm_eval_batch(model: Model, precision, batch: Batch, ws: Workspace, cost_out
     prec = PRECISIONS.get(precision, precision)
     check(lib().cm_eval_batch(model.handle, int(prec), ctypes.byref(batch.c), ws.handle,
                               _ptr(cost_out), _stream_handle(stream)))
+
+
+def cm_hoist_stages(model: Model, precision, batch: Batch, U_out, stream=None):
+    """Per-stage hoisted first-layer rows of the batch into U_out (float32
+    device tensor of at least sum(n_stages) * 32 values)."""
+    prec = PRECISIONS.get(precision, precision)
+    check(lib().cm_hoist_stages(model.handle, int(prec), ctypes.byref(batch.c), _ptr(U_out),
+                                _stream_handle(stream)))
+
+
+def cm_eval_hoisted(model: Model, precision, batch: Batch, U, ws: Workspace, cost_out,
+                    stream=None):
+    """cm_eval_batch reading hoisted rows U written by cm_hoist_stages."""
+    prec = PRECISIONS.get(precision, precision)
+    check(lib().cm_eval_hoisted(model.handle, int(prec), ctypes.byref(batch.c), _ptr(U),
+                                ws.handle, _ptr(cost_out), _stream_handle(stream)))
 
 
 def cm_topk_per_query(cost, batch: Batch, k: int, ws: Workspace, idx_out, val_out,

@@ -24,7 +24,8 @@ CM_STAGE_CHUNK = 16
 # Every function the header declares, for the export check.
 EXPORTS = (
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
-    "cm_eval_batch", "cm_topk_per_query", "cm_last_error", "cm_version",
+    "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
+    "cm_last_error", "cm_version",
 )
 
 
@@ -74,9 +75,12 @@ def lib():
         L.cm_workspace_create.argtypes = [ctypes.POINTER(cm_workspace_desc), ctypes.POINTER(vp)]
         L.cm_workspace_destroy.argtypes = [vp]
         L.cm_eval_batch.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp, vp]
+        L.cm_hoist_stages.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp]
+        L.cm_eval_hoisted.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp, vp, vp]
         L.cm_topk_per_query.argtypes = [vp, ctypes.POINTER(cm_batch), i32, vp, vp, vp, vp]
         for f in ("cm_model_create", "cm_model_destroy", "cm_workspace_create",
-                  "cm_workspace_destroy", "cm_eval_batch", "cm_topk_per_query"):
+                  "cm_workspace_destroy", "cm_eval_batch", "cm_hoist_stages",
+                  "cm_eval_hoisted", "cm_topk_per_query"):
             getattr(L, f).restype = i32
         L.cm_last_error.restype = ctypes.c_char_p
         L.cm_last_error.argtypes = []

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -92,8 +93,6 @@ void free_model(cm::Model &m)
 void free_ws(cm::Workspace &w)
 {
     if (w.d_U) (void)hipFree(w.d_U);
-    if (w.d_part) (void)hipFree(w.d_part);
-    if (w.d_ecnt) (void)hipFree(w.d_ecnt);
     if (w.d_tpart) (void)hipFree(w.d_tpart);
     if (w.d_tcnt) (void)hipFree(w.d_tcnt);
     w = cm::Workspace{};
@@ -204,8 +203,10 @@ cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model 
         for (int lane = 0; lane < 64; ++lane) {
             uint16_t hi[8], lo[8];
             for (int j = 0; j < 8; ++j) {
-                const int mrow = lane & 31, k = st * 16 + (lane >> 5) * 8 + j;
-                split_bf16(k < FS ? Wf[mrow][k] : 0.0, hi[j], lo[j]);
+                // k-slot (step st, lane half hf, element j) -> schedule feature
+                const int mrow = lane & 31, hf = lane >> 5;
+                const int k = st < 2 ? st * 16 + hf * 8 + j : (j < 4 ? 32 + hf * 4 + j : -1);
+                split_bf16(k >= 0 ? Wf[mrow][k] : 0.0, hi[j], lo[j]);
             }
             std::memcpy(&pk.a1[0][st][lane], hi, 16);
             std::memcpy(&pk.a1[1][st][lane], lo, 16);
@@ -271,21 +272,16 @@ cm_status cm_workspace_create(const cm_workspace_desc *d, cm_workspace **out)
         delete W;
         return fail(CM_EDEVICE, "no HIP device");
     }
-    w.part_cap = d->max_rows / SCHUNK + d->max_cands + 1;
-    w.ecnt_cap = d->max_cands / TILE_ROWS + d->max_queries + 1;
     w.tpart_cap = (d->max_cands / TOPK_TILE + d->max_queries + 1) * (int64_t)d->max_k;
     cm_status st;
     if ((st = dev_alloc(&w.d_U, (size_t)d->max_stages * H, "hoisted stage vectors")) != CM_OK ||
-        (st = dev_alloc(&w.d_part, (size_t)w.part_cap, "partial sums")) != CM_OK ||
-        (st = dev_alloc(&w.d_ecnt, (size_t)w.ecnt_cap, "eval counters")) != CM_OK ||
         (st = dev_alloc(&w.d_tpart, (size_t)w.tpart_cap, "beam lists")) != CM_OK ||
         (st = dev_alloc(&w.d_tcnt, (size_t)QMAX, "beam counters")) != CM_OK) {
         free_ws(w);
         delete W;
         return st;
     }
-    if (hipMemset(w.d_ecnt, 0, w.ecnt_cap * sizeof(int32_t)) != hipSuccess ||
-        hipMemset(w.d_tcnt, 0, QMAX * sizeof(int32_t)) != hipSuccess ||
+    if (hipMemset(w.d_tcnt, 0, QMAX * sizeof(int32_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         free_ws(w);
         delete W;
@@ -303,10 +299,119 @@ cm_status cm_workspace_destroy(cm_workspace *W)
     return CM_OK;
 }
 
-cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
-                        cm_workspace *W, float *cost_out, cm_stream stream)
+}  // extern "C"
+
+namespace {
+
+// Descriptors of queries [g0, g0 + ng) for one launch.  Hoisted rows of the
+// batch are laid out in batch order: query q's rows start at (sum of n_stages
+// of the queries before it) * 32 floats.
+void fill_eval_launch(cm::EvalLaunch &L, const cm_batch *b, int32_t g0, int32_t ng,
+                      int64_t stage_prefix, cm_precision prec)
 {
     using namespace cm;
+    std::memset(&L, 0, sizeof L);
+    L.nq = ng;
+    // hoisted rows stay in batch order; workgroups are issued longest stage
+    // part first so the longest-running ones start earliest
+    int64_t row_of[QMAX];
+    int32_t order[QMAX];
+    int64_t r = 0;
+    for (int32_t j = 0; j < ng; ++j) {
+        row_of[j] = r;
+        r += b->queries[g0 + j].n_stages;
+        order[j] = j;
+    }
+    if (prec != CM_FP32) {
+        auto per_wave = [&](int32_t j) {
+            const int S = b->queries[g0 + j].n_stages;
+            return (S + stage_parts(S) - 1) / stage_parts(S);
+        };
+        std::stable_sort(order, order + ng,
+                         [&](int32_t x, int32_t y) { return per_wave(x) > per_wave(y); });
+    }
+    int64_t hrow = 0, task = 0;
+    for (int32_t jj = 0; jj < ng; ++jj) {
+        const int32_t j = order[jj];
+        const cm_query &Q = b->queries[g0 + j];
+        EvalQ &e = L.q[jj];
+        e.S = Q.n_stages;
+        e.N = Q.n_cands;
+        e.pipe_off = Q.pipe_off;
+        e.sched_off = Q.sched_off;
+        e.terms_off = Q.terms_off;
+        e.cost_off = Q.cost_off;
+        e.u_off = (stage_prefix + row_of[j]) * H;
+        e.hrow0 = (int32_t)hrow;
+        e.task0 = (int32_t)task;
+        e.parts = stage_parts(Q.n_stages);
+        hrow += Q.n_stages;
+        if (prec == CM_FP32) {
+            task += cdiv(Q.n_cands, 64);
+        } else {
+            const int64_t tiles = cdiv(Q.n_cands, TILE_ROWS);
+            task += cdiv(tiles, EVAL_WAVES / e.parts);
+        }
+    }
+    L.ntasks = (int32_t)task;
+    L.nstages = (int32_t)hrow;
+}
+
+cm_status check_queries(const cm_batch *b)
+{
+    if (!b) return fail(CM_EINVAL, "batch is NULL");
+    if (b->n_queries < 0) return fail(CM_EINVAL, "n_queries < 0");
+    if (b->n_queries > 0 && !b->queries) return fail(CM_EINVAL, "queries is NULL");
+    int64_t stages = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) {
+        const cm_query &Q = b->queries[q];
+        if (Q.n_stages < 1) return fail(CM_EINVAL, "query %d: n_stages %d < 1", q, Q.n_stages);
+        if (Q.n_cands < 0) return fail(CM_EINVAL, "query %d: n_cands %d < 0", q, Q.n_cands);
+        if (Q.pipe_off < 0) return fail(CM_EINVAL, "query %d: negative offset", q);
+        stages += Q.n_stages;
+    }
+    if (stages > INT32_MAX / 2) return fail(CM_E2BIG, "too many stages");
+    if (b->n_queries > 0 && !b->pipe) return fail(CM_EINVAL, "pipe is NULL");
+    return CM_OK;
+}
+
+cm_status hoist_impl(const cm_model *M, cm_precision prec, const cm_batch *b, float *U,
+                     hipStream_t s)
+{
+    using namespace cm;
+    int64_t stage_prefix = 0;
+    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
+        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
+        EvalLaunch L;
+        fill_eval_launch(L, b, g0, ng, stage_prefix, prec);
+        CM_HIP(launch_hoist(L, M->m, prec != CM_FP32, b->pipe, U, s));
+        stage_prefix += L.nstages;
+    }
+    return CM_OK;
+}
+
+cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, const float *U,
+                    const cm::Workspace &w, float *cost_out, hipStream_t s)
+{
+    using namespace cm;
+    int64_t stage_prefix = 0;
+    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
+        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
+        EvalLaunch L;
+        fill_eval_launch(L, b, g0, ng, stage_prefix, prec);
+        if (prec == CM_FP32)
+            CM_HIP(launch_eval_fp32(L, M->m, (const float *)b->sched, b->terms, U, cost_out, s));
+        else
+            CM_HIP(launch_eval_bf16(L, M->m, (const uint16_t *)b->sched, b->terms, U, cost_out,
+                                    s));
+        stage_prefix += L.nstages;
+    }
+    return CM_OK;
+}
+
+cm_status check_eval(const cm_model *M, cm_precision prec, const cm_batch *b,
+                     const cm_workspace *W, const float *cost_out, int64_t *cands)
+{
     if (!M || !W) return fail(CM_EINVAL, "model or workspace is NULL");
     if (prec != CM_FP32 && prec != CM_BF16)
         return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
@@ -314,56 +419,52 @@ cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
     if (st != CM_OK) return st;
     if ((st = check_device(M->m.device)) != CM_OK) return st;
     if (W->w.device != M->m.device) return fail(CM_EINVAL, "model and workspace devices differ");
-    int64_t cands = 0;
-    for (int32_t q = 0; q < b->n_queries; ++q) cands += b->queries[q].n_cands;
-    if (cands == 0) return CM_OK;
-    if (!cost_out) return fail(CM_EINVAL, "cost_out is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    const Workspace &w = W->w;
-
-    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
-        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
-        EvalLaunch L;
-        std::memset(&L, 0, sizeof L);
-        L.nq = ng;
-        int64_t stage = 0, task = 0, cnt = 0, part = 0;
-        for (int32_t j = 0; j < ng; ++j) {
-            const cm_query &Q = b->queries[g0 + j];
-            EvalQ &e = L.q[j];
-            e.S = Q.n_stages;
-            e.N = Q.n_cands;
-            e.pipe_off = Q.pipe_off;
-            e.sched_off = Q.sched_off;
-            e.terms_off = Q.terms_off;
-            e.cost_off = Q.cost_off;
-            e.stage0 = (int32_t)stage;
-            e.task0 = (int32_t)task;
-            e.cnt0 = (int32_t)cnt;
-            e.nchunk = (int32_t)cdiv(Q.n_stages, SCHUNK);
-            e.part0 = part;
-            stage += Q.n_stages;
-            if (prec == CM_FP32) {
-                task += cdiv(Q.n_cands, 64);
-            } else {
-                const int64_t tiles = cdiv(Q.n_cands, TILE_ROWS);
-                task += tiles * e.nchunk;
-                cnt += tiles;
-                if (e.nchunk > 1) part += (int64_t)e.nchunk * Q.n_cands;
-            }
-        }
-        if (task > INT32_MAX || part > w.part_cap || cnt > w.ecnt_cap)
-            return fail(CM_E2BIG, "batch exceeds workspace scratch");
-        L.ntasks = (int32_t)task;
-        L.nstages = (int32_t)stage;
-        CM_HIP(launch_hoist(L, M->m, prec != CM_FP32, b->pipe, w.d_U, s));
-        if (prec == CM_FP32)
-            CM_HIP(launch_eval_fp32(L, M->m, (const float *)b->sched, b->terms, w.d_U, cost_out,
-                                    s));
-        else
-            CM_HIP(launch_eval_bf16(L, M->m, (const uint16_t *)b->sched, b->terms, w.d_U,
-                                    w.d_part, w.d_ecnt, cost_out, s));
-    }
+    *cands = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) *cands += b->queries[q].n_cands;
+    if (*cands > 0 && !cost_out) return fail(CM_EINVAL, "cost_out is NULL");
     return CM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cm_status cm_hoist_stages(const cm_model *M, cm_precision prec, const cm_batch *b, float *U_out,
+                          cm_stream stream)
+{
+    if (!M) return fail(CM_EINVAL, "model is NULL");
+    if (prec != CM_FP32 && prec != CM_BF16)
+        return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
+    cm_status st = check_queries(b);
+    if (st != CM_OK) return st;
+    if (b->n_queries == 0) return CM_OK;
+    if (!U_out) return fail(CM_EINVAL, "U_out is NULL");
+    if (!aligned(U_out, 16)) return fail(CM_EINVAL, "U_out must be 16-byte aligned");
+    if ((st = check_device(M->m.device)) != CM_OK) return st;
+    return hoist_impl(M, prec, b, U_out, (hipStream_t)stream);
+}
+
+cm_status cm_eval_hoisted(const cm_model *M, cm_precision prec, const cm_batch *b,
+                          const float *U, cm_workspace *W, float *cost_out, cm_stream stream)
+{
+    int64_t cands = 0;
+    cm_status st = check_eval(M, prec, b, W, cost_out, &cands);
+    if (st != CM_OK) return st;
+    if (cands == 0) return CM_OK;
+    if (!U || !aligned(U, 16)) return fail(CM_EINVAL, "U is NULL or not 16-byte aligned");
+    return eval_impl(M, prec, b, U, W->w, cost_out, (hipStream_t)stream);
+}
+
+cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
+                        cm_workspace *W, float *cost_out, cm_stream stream)
+{
+    int64_t cands = 0;
+    cm_status st = check_eval(M, prec, b, W, cost_out, &cands);
+    if (st != CM_OK) return st;
+    if (cands == 0) return CM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = hoist_impl(M, prec, b, W->w.d_U, s)) != CM_OK) return st;
+    return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, s);
 }
 
 cm_status cm_topk_per_query(const float *cost, const cm_batch *b, int32_t k, cm_workspace *W,

@@ -28,9 +28,18 @@ constexpr int N_PARAMS = OFF_B2 + C;
 static_assert(N_PARAMS == CM_N_PARAMS, "parameter layout");
 
 constexpr int QMAX = 32;            // queries per kernel launch (descriptors by value)
-constexpr int SCHUNK = CM_STAGE_CHUNK;
-constexpr int TILE_ROWS = 32;       // candidates per wave task of the bf16 evaluator
-constexpr int TOPK_TILE = 2048;     // candidates per wave task of the selection
+constexpr int TILE_ROWS = 32;       // candidates per wave of the bf16 evaluator
+constexpr int EVAL_WAVES = 8;       // waves per workgroup of the bf16 evaluator
+
+// Stage parts of the bf16 evaluator: a query's stages are split into P
+// contiguous, near-equal parts, one wave each; the parts' compensated sums
+// are combined in ascending order inside the workgroup.  P depends only on
+// the query's stage count, so results never depend on the batch.
+__host__ __device__ constexpr int stage_parts(int S)
+{
+    return S <= CM_STAGE_CHUNK / 2 ? 1 : S <= CM_STAGE_CHUNK ? 2 : S <= 2 * CM_STAGE_CHUNK ? 4 : 8;
+}
+constexpr int TOPK_TILE = 4096;     // candidates per workgroup of the selection
 
 // bf16 split-product operands of the two dense layers, laid out as the
 // 32x32x16 bf16 matrix-core instruction reads them: 8 bf16 (16 bytes) per
@@ -52,10 +61,6 @@ struct Workspace {
     int device = 0;
     cm_workspace_desc cap{};
     float *d_U = nullptr;          // [stages][32] hoisted first-layer input
-    float2 *d_part = nullptr;      // partial (sum, comp) per (chunk, candidate)
-    int64_t part_cap = 0;
-    int32_t *d_ecnt = nullptr;     // arrival counters per (query, row tile)
-    int64_t ecnt_cap = 0;
     uint64_t *d_tpart = nullptr;   // per-tile beam lists
     int64_t tpart_cap = 0;
     int32_t *d_tcnt = nullptr;     // arrival counters per query (selection)
@@ -65,16 +70,16 @@ struct Workspace {
 struct EvalQ {
     int32_t S, N;
     int64_t pipe_off, sched_off, terms_off, cost_off;
-    int32_t stage0;    // first row of this query in the hoisted U buffer
-    int32_t task0;     // first task (row tile x stage chunk) of this query
-    int32_t cnt0;      // first arrival counter of this query
-    int32_t nchunk;    // ceil(S / SCHUNK)
-    int64_t part0;     // first partial of this query ([nchunk][N])
+    int64_t u_off;     // offset (floats) of this query's hoisted rows U[S][32]
+    int32_t hrow0;     // first hoist block of this query in the launch
+    int32_t task0;     // first workgroup (bf16) or thread block (fp32) of this query
+    int32_t parts;     // stage parts P (bf16)
+    int32_t pad;
 };
 
 struct EvalLaunch {
     int32_t nq;
-    int32_t ntasks;    // tasks (bf16) or thread blocks (fp32)
+    int32_t ntasks;    // workgroups (bf16) or thread blocks (fp32)
     int32_t nstages;   // hoist blocks
     int32_t pad;
     EvalQ q[QMAX];
@@ -102,8 +107,7 @@ hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, const fl
 hipError_t launch_eval_fp32(const EvalLaunch &L, const Model &m, const float *sched,
                             const float *terms, const float *U, float *cost, hipStream_t st);
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
-                            const float *terms, const float *U, float2 *part, int32_t *cnt,
-                            float *cost, hipStream_t st);
+                            const float *terms, const float *U, float *cost, hipStream_t st);
 hipError_t launch_topk(const TopkLaunch &L, const float *cost, uint64_t *tpart, int32_t *tcnt,
                        int32_t *idx_out, float *val_out, hipStream_t st);
 

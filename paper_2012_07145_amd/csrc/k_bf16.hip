@@ -1,9 +1,12 @@
 // k_bf16.hip -- the bf16 matrix-core evaluator of the cost model (Sec. 5.2).
 //
-// Work unit ("task") = one wavefront x (32 candidates of one query) x (one
-// chunk of up to CM_STAGE_CHUNK consecutive stages).  Per stage the wave
+// Work unit = one wavefront x (32 candidates of one query) x (one part of the
+// query's stages; stage_parts() splits them into 1, 2, 4 or 8 contiguous
+// parts by stage count alone).  A workgroup of 8 waves holds every part of
+// its row tiles.  Per stage the wave
 //   1. loads the 32 candidates' bf16 schedule features (stage-major rows of
-//      80 bytes, 16 bytes per lane per load) and their float32 cost terms;
+//      80 bytes; each row is split over two lanes, 40 bytes each) and their
+//      float32 cost terms, one stage ahead of the arithmetic;
 //   2. takes log2(1 + x) in float32 (ln 2 is folded into the weights, so the
 //      layer sees log1p(x)) and splits it into high and low bf16 parts;
 //   3. runs the first layer as D[hidden][cand] = Wf . X^T on the 32x32x16 bf16
@@ -18,9 +21,10 @@
 //   5. applies the ReLU to the 8 coefficients, dots them with the 8 cost
 //      terms (two lanes hold four each and exchange halves) and adds the
 //      stage prediction to a Kahan-compensated float32 sum (App. B).
-// A chunk's (sum, compensation) pair goes to the workspace; the last wave to
-// finish a row tile combines the chunks in ascending order, so the result of
-// a candidate depends only on its query, never on the batch or on timing.
+// Each part's (sum, compensation) pair goes through LDS and the first wave of
+// the tile combines the parts in ascending order, so the result of a
+// candidate depends only on its query, never on the batch or on timing, and
+// no device-wide synchronisation is needed.
 #include "cm_internal.h"
 
 namespace cm {
@@ -36,30 +40,74 @@ __device__ inline uint32_t pack_bf16x2(float a, float b)
     return __builtin_bit_cast(uint32_t, v);
 }
 
-__device__ inline float bf16lo_to_f32(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ inline float bf16hi_to_f32(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+// A packed pair of bf16 constants kept in a register.  The dot instruction
+// below must not see them as inline constants: an inline constant in a
+// packed-bf16 operand does not select the same halves as the compiler
+// assumes, so the value is hidden from constant folding.
+__device__ inline bf16x2 pair_reg(uint32_t bits)
+{
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "i"(bits));
+    return __builtin_bit_cast(bf16x2, v);
+}
 
-// Two float values -> (high bf16 pair, low bf16 pair) with a ~= hi + lo.
-__device__ inline void split2(float a, float b, uint32_t &hi, uint32_t &lo)
+// c + (one bf16 of w) * (the matching bf16 of m): the product of two bf16
+// values is exact in float32 and the sum is rounded once.
+__device__ inline float dot(uint32_t w, bf16x2 m, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), m, c, false);
+}
+
+struct Pairs {
+    bf16x2 one_lo, one_hi, neg_lo, neg_hi;  // (1,0) (0,1) (-1,0) (0,-1)
+};
+
+__device__ inline Pairs make_pairs()
+{
+    return Pairs{pair_reg(0x00003f80u), pair_reg(0x3f800000u), pair_reg(0x0000bf80u),
+                 pair_reg(0xbf800000u)};
+}
+
+// Two float values -> (high bf16 pair, low bf16 pair) with a ~= hi + lo:
+// hi rounds to nearest, lo = a - hi is exact in float32 before its rounding.
+__device__ inline void split2(float a, float b, uint32_t &hi, uint32_t &lo, const Pairs &k)
 {
     hi = pack_bf16x2(a, b);
-    lo = pack_bf16x2(a - bf16lo_to_f32(hi), b - bf16hi_to_f32(hi));
+    lo = pack_bf16x2(dot(hi, k.neg_lo, a), dot(hi, k.neg_hi, b));
 }
 
 // 8 raw bf16 features -> high/low bf16 operands of log2(1 + x).
-__device__ inline void log_split(uint4 raw, bf16x8 &hi, bf16x8 &lo)
+__device__ inline void log_split(uint4 raw, bf16x8 &hi, bf16x8 &lo, const Pairs &k)
 {
     uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
     uint32_t h[4], l[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const float y0 = __builtin_amdgcn_logf(1.0f + bf16lo_to_f32(w[d]));
-        const float y1 = __builtin_amdgcn_logf(1.0f + bf16hi_to_f32(w[d]));
-        split2(y0, y1, h[d], l[d]);
+        const float y0 = __builtin_amdgcn_logf(dot(w[d], k.one_lo, 1.0f));
+        const float y1 = __builtin_amdgcn_logf(dot(w[d], k.one_hi, 1.0f));
+        split2(y0, y1, h[d], l[d], k);
     }
     hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
+
+// 4 raw bf16 features (plus 4 zero slots) -> high/low operands.
+__device__ inline void log_split4(uint2 raw, bf16x8 &hi, bf16x8 &lo, const Pairs &k)
+{
+    uint32_t w[2] = {raw.x, raw.y};
+    uint32_t h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const float y0 = __builtin_amdgcn_logf(dot(w[d], k.one_lo, 1.0f));
+        const float y1 = __builtin_amdgcn_logf(dot(w[d], k.one_hi, 1.0f));
+        split2(y0, y1, h[d], l[d], k);
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+// max(x, 0) on the bit pattern: negative floats are negative integers
+__device__ inline float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 __device__ inline void kahan_add(float &s, float &c, float v)
 {
@@ -82,28 +130,55 @@ __device__ inline int find_task_query(const EvalLaunch &L, int t)
     return q;
 }
 
-__global__ __launch_bounds__(256) void k_eval_bf16(EvalLaunch L, const Bf16Pack *__restrict__ pk,
-                                                   const uint16_t *__restrict__ sched,
-                                                   const float *__restrict__ terms,
-                                                   const float *__restrict__ U,
-                                                   float2 *__restrict__ part,
-                                                   int32_t *__restrict__ cnt,
-                                                   float *__restrict__ cost)
+// Sum of a value held by lane l and lane l ^ 32, identical in both lanes.
+__device__ inline float add_halves(float v)
 {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// One stage's operands for one lane: features 16*st + 8*hf .. +8 for st = 0, 1,
+// features 32 + 4*hf .. +4, and cost terms 4*hf .. +4.
+struct StageIn {
+    uint4 x0, x1;
+    uint2 x2;
+    float4 t;
+};
+
+// xs, ts: the stage's rows (uniform); xo, x2o, to: this lane's byte offsets
+__device__ inline void load_stage(StageIn &in, const char *xs, const char *ts, uint32_t xo,
+                                  uint32_t x2o, uint32_t to)
+{
+    in.x0 = *reinterpret_cast<const uint4 *>(xs + xo);
+    in.x1 = *reinterpret_cast<const uint4 *>(xs + xo + 32);
+    in.x2 = *reinterpret_cast<const uint2 *>(xs + x2o);
+    in.t = *reinterpret_cast<const float4 *>(ts + to);
+}
+
+__global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_eval_bf16(
+    EvalLaunch L, const Bf16Pack *__restrict__ pk, const uint16_t *__restrict__ sched,
+    const float *__restrict__ terms, const float *__restrict__ U, float *__restrict__ cost)
+{
+    __shared__ float2 lds_part[EVAL_WAVES][TILE_ROWS];
     const int lane = threadIdx.x & 63;
-    const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (task >= L.ntasks) return;
-    const int q = find_task_query(L, task);
+    const int wave = threadIdx.x >> 6;
+    const int q = find_task_query(L, blockIdx.x);
     const EvalQ Q = L.q[q];
-    const int local = task - Q.task0;
-    const int tile = local / Q.nchunk;
-    const int chunk = local - tile * Q.nchunk;
+    const int P = Q.parts;
+    // this workgroup holds EVAL_WAVES / P row tiles; wave -> (tile, part)
+    const int tile = (blockIdx.x - Q.task0) * (EVAL_WAVES / P) + wave / P;
+    const int part = wave % P;
     const int n = lane & 31;
     const int hf = lane >> 5;
     const int i = tile * TILE_ROWS + n;
     const bool valid = i < Q.N;
-    const int s0 = chunk * SCHUNK;
-    const int s1 = min(Q.S, s0 + SCHUNK);
+    // rows past the end of the query read the last row instead: every load
+    // stays in bounds and the results of those rows are never stored
+    const int ic = valid ? i : Q.N - 1;
+    // stages [s0, s1) of this part; a tile past the query's end does no work
+    const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
+    const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
 
     bf16x8 A1h[3], A1l[3], A2h[2], A2l[2];
 #pragma unroll
@@ -119,112 +194,120 @@ __global__ __launch_bounds__(256) void k_eval_bf16(EvalLaunch L, const Bf16Pack 
     float b2v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) b2v[r] = pk->b2[hf * 4 + r];
+    const Pairs kp = make_pairs();
 
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+    // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart
+    const int64_t xstep = (int64_t)Q.N * FS * 2;
+    const int64_t tstep = (int64_t)Q.N * C * 4;
+    const char *xs = reinterpret_cast<const char *>(sched + Q.sched_off) + s0 * xstep;
+    const char *ts = reinterpret_cast<const char *>(terms + Q.terms_off) + s0 * tstep;
+    const uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
+    const uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
+    const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
+    const float4 *urow = reinterpret_cast<const float4 *>(U + Q.u_off + (int64_t)s0 * H);
+
     float sum = 0.f, comp = 0.f;
-    for (int s = s0; s < s1; ++s) {
-        const int64_t r = (int64_t)s * Q.N + i;
-        const uint4 *xr = reinterpret_cast<const uint4 *>(sched + Q.sched_off + r * FS);
-        const uint4 x0 = valid ? xr[hf] : zero4;
-        const uint4 x1 = valid ? xr[2 + hf] : zero4;
-        const uint4 x2 = (valid && hf == 0) ? xr[4] : zero4;
-        float4 tv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (valid) tv = *reinterpret_cast<const float4 *>(terms + Q.terms_off + r * C + hf * 4);
-
-        // accumulator starts from the hoisted per-stage vector, in the
-        // matrix core's output order: register g*4+j <-> hidden g*8 + hf*4 + j
-        const float4 *up = reinterpret_cast<const float4 *>(U + (int64_t)(Q.stage0 + s) * H);
-        f32x16 acc;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const float4 u4 = up[g * 2 + hf];
-            acc[g * 4 + 0] = u4.x;
-            acc[g * 4 + 1] = u4.y;
-            acc[g * 4 + 2] = u4.z;
-            acc[g * 4 + 3] = u4.w;
-        }
-        bf16x8 bh, bl;
-        log_split(x0, bh, bl);
-        acc = mfma(A1h[0], bh, acc);
-        acc = mfma(A1l[0], bh, acc);
-        acc = mfma(A1h[0], bl, acc);
-        log_split(x1, bh, bl);
-        acc = mfma(A1h[1], bh, acc);
-        acc = mfma(A1l[1], bh, acc);
-        acc = mfma(A1h[1], bl, acc);
-        log_split(x2, bh, bl);
-        acc = mfma(A1h[2], bh, acc);
-        acc = mfma(A1l[2], bh, acc);
-        acc = mfma(A1h[2], bl, acc);
-
-        f32x16 acc2;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc2[k] = b2v[k];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            uint32_t hh[4], hl[4];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const float a = fmaxf(acc[t * 8 + 2 * d], 0.f);
-                const float b = fmaxf(acc[t * 8 + 2 * d + 1], 0.f);
-                split2(a, b, hh[d], hl[d]);
+    if (s0 < s1) {
+        StageIn cur, nxt;
+        load_stage(cur, xs, ts, xo, x2o, to);
+        for (int s = s0; s < s1; ++s) {
+            // prefetch the next stage; the last iteration re-reads its own
+            // stage (cache-resident) so that every iteration issues the same loads
+            if (s + 1 < s1) {
+                xs += xstep;
+                ts += tstep;
             }
-            const bf16x8 Hh = __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
-            const bf16x8 Hl = __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
-            acc2 = mfma(A2h[t], Hh, acc2);
-            acc2 = mfma(A2l[t], Hh, acc2);
-            acc2 = mfma(A2h[t], Hl, acc2);
+            load_stage(nxt, xs, ts, xo, x2o, to);
+
+            // first layer: accumulator starts from U[s]; register g*4+j holds
+            // hidden unit g*8 + hf*4 + j
+            f32x16 acc;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float4 u4 = urow[g * 2 + hf];
+                acc[g * 4 + 0] = u4.x;
+                acc[g * 4 + 1] = u4.y;
+                acc[g * 4 + 2] = u4.z;
+                acc[g * 4 + 3] = u4.w;
+            }
+            urow += H / 4;
+            bf16x8 bh, bl;
+            log_split(cur.x0, bh, bl, kp);
+            acc = mfma(A1h[0], bh, acc);
+            acc = mfma(A1l[0], bh, acc);
+            acc = mfma(A1h[0], bl, acc);
+            log_split(cur.x1, bh, bl, kp);
+            acc = mfma(A1h[1], bh, acc);
+            acc = mfma(A1l[1], bh, acc);
+            acc = mfma(A1h[1], bl, acc);
+            log_split4(cur.x2, bh, bl, kp);
+            acc = mfma(A1h[2], bh, acc);
+            acc = mfma(A1l[2], bh, acc);
+            acc = mfma(A1h[2], bl, acc);
+
+            // coefficient layer (output registers 0..3 are the 8 real
+            // outputs); its bias is added after the products
+            f32x16 acc2;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                uint32_t hh[4], hl[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const float a = relu(acc[t * 8 + 2 * d]);
+                    const float b = relu(acc[t * 8 + 2 * d + 1]);
+                    split2(a, b, hh[d], hl[d], kp);
+                }
+                const bf16x8 Hh =
+                    __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
+                const bf16x8 Hl =
+                    __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
+                acc2 = mfma(A2h[t], Hh, acc2);
+                acc2 = mfma(A2l[t], Hh, acc2);
+                acc2 = mfma(A2h[t], Hl, acc2);
+            }
+            // lanes hf=0 hold coefficients 0..3 of their candidate, hf=1 hold 4..7
+            float v = relu(acc2[0] + b2v[0]) * cur.t.x;
+            v = fmaf(relu(acc2[1] + b2v[1]), cur.t.y, v);
+            v = fmaf(relu(acc2[2] + b2v[2]), cur.t.z, v);
+            v = fmaf(relu(acc2[3] + b2v[3]), cur.t.w, v);
+            kahan_add(sum, comp, add_halves(v));
+            // the next stage's loads were issued before this stage's
+            // arithmetic; pin them to this iteration so the compiler cannot
+            // sink them into the iteration that consumes them
+            asm volatile("" : "+v"(nxt.x0.x), "+v"(nxt.x0.y), "+v"(nxt.x0.z), "+v"(nxt.x0.w),
+                         "+v"(nxt.x1.x), "+v"(nxt.x1.y), "+v"(nxt.x1.z), "+v"(nxt.x1.w),
+                         "+v"(nxt.x2.x), "+v"(nxt.x2.y), "+v"(nxt.t.x), "+v"(nxt.t.y),
+                         "+v"(nxt.t.z), "+v"(nxt.t.w));
+            cur = nxt;
         }
-        // lanes hf=0 hold coefficients 0..3 of their candidate, hf=1 hold 4..7
-        float v = fmaxf(acc2[0], 0.f) * tv.x;
-        v = fmaf(fmaxf(acc2[1], 0.f), tv.y, v);
-        v = fmaf(fmaxf(acc2[2], 0.f), tv.z, v);
-        v = fmaf(fmaxf(acc2[3], 0.f), tv.w, v);
-        v += __shfl_xor(v, 32);
-        kahan_add(sum, comp, v);
     }
 
-    const int64_t cidx = Q.cost_off + i;
-    if (Q.nchunk == 1) {
-        if (hf == 0 && valid) {
-            float S = 0.f, Cc = 0.f;
-            kahan_add(S, Cc, sum);
-            kahan_add(S, Cc, -comp);
-            cost[cidx] = S - Cc;
-        }
-        return;
+    // combine the parts of each tile in ascending order
+    if (P > 1) {
+        if (hf == 0) lds_part[wave][n] = make_float2(sum, comp);
+        __syncthreads();
     }
-    if (hf == 0 && valid) part[Q.part0 + (int64_t)chunk * Q.N + i] = make_float2(sum, comp);
-    __threadfence();
-    int old = 0;
-    if (lane == 0) old = atomicAdd(&cnt[Q.cnt0 + tile], 1);
-    old = __shfl(old, 0);
-    if (old != Q.nchunk - 1) return;
-    __threadfence();
-    if (hf == 0 && valid) {
+    if (part == 0 && hf == 0 && valid) {
         float S = 0.f, Cc = 0.f;
-        for (int ch = 0; ch < Q.nchunk; ++ch) {
-            const float2 p = part[Q.part0 + (int64_t)ch * Q.N + i];
-            kahan_add(S, Cc, p.x);
-            kahan_add(S, Cc, -p.y);
+        for (int p = 0; p < P; ++p) {
+            const float2 pc = P > 1 ? lds_part[wave + p][n] : make_float2(sum, comp);
+            kahan_add(S, Cc, pc.x);
+            kahan_add(S, Cc, -pc.y);
         }
-        cost[cidx] = S - Cc;
+        cost[Q.cost_off + i] = S - Cc;
     }
-    if (lane == 0) atomicExch(&cnt[Q.cnt0 + tile], 0);
 }
 
 }  // namespace
 
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
-                            const float *terms, const float *U, float2 *part, int32_t *cnt,
-                            float *cost, hipStream_t st)
+                            const float *terms, const float *U, float *cost, hipStream_t st)
 {
     if (L.ntasks == 0) return hipSuccess;
-    const int blocks = (L.ntasks + 3) / 4;
-    hipLaunchKernelGGL(k_eval_bf16, dim3(blocks), dim3(256), 0, st, L, m.d_bf16, sched, terms, U,
-                       part, cnt, cost);
+    hipLaunchKernelGGL(k_eval_bf16, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L, m.d_bf16,
+                       sched, terms, U, cost);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ __device__ inline int find_query(const EvalLaunch &L, int t, bool by_stage)
     // Largest q with start(q) <= t.  Uniform across the workgroup.
     int q = 0;
     for (int j = 1; j < L.nq; ++j) {
-        int start = by_stage ? L.q[j].stage0 : L.q[j].task0;
+        int start = by_stage ? L.q[j].hrow0 : L.q[j].task0;
         if (start <= t) q = j;
     }
     return q;
@@ -33,16 +33,18 @@ __global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restr
                                               const float *__restrict__ pipe,
                                               float *__restrict__ U)
 {
+    __shared__ float lp[FP];
     __shared__ float ep[E];
-    const int row = blockIdx.x;  // global stage row within the launch
-    const int q = find_query(L, row, true);
-    const int s = row - L.q[q].stage0;
+    const int q = find_query(L, blockIdx.x, true);
+    const int s = blockIdx.x - L.q[q].hrow0;
     const float *p = pipe + L.q[q].pipe_off + (int64_t)s * FP;
     const int t = threadIdx.x;
+    if (t < FP) lp[t] = log1pf(p[t]);
+    __syncthreads();
     if (t < E) {
         const float *w = params + OFF_WP + t * FP;
         float a = params[OFF_BP + t];
-        for (int f = 0; f < FP; ++f) a = fmaf(w[f], log1pf(p[f]), a);
+        for (int f = 0; f < FP; ++f) a = fmaf(w[f], lp[f], a);
         ep[t] = a;
     }
     __syncthreads();
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restr
         float a = params[OFF_B1 + t];
         for (int e = 0; e < E; ++e) a = fmaf(w[e], ep[e], a);
         if (fold) a += beta[t];
-        U[(int64_t)row * H + t] = a;
+        U[L.q[q].u_off + (int64_t)s * H + t] = a;
     }
 }
 
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(64) void k_eval_fp32(EvalLaunch L, const float *__r
             for (int f = 0; f < FS; ++f) a = fmaf(Ws[e * FS + f], x[f], a);
             es[e] = a;
         }
-        const float *u = U + (int64_t)(Q.stage0 + s) * H;
+        const float *u = U + Q.u_off + (int64_t)s * H;
         float h[H];
 #pragma unroll
         for (int j = 0; j < H; ++j) {

@@ -6,119 +6,276 @@
 // ranks after +inf, so the unsigned order of the keys is exactly "ascending
 // cost, ties by lower index, NaN last", and keys are unique.
 //
-// One wavefront per tile of TOPK_TILE candidates keeps a sorted list of the
-// 64*M smallest keys seen (M registers per lane, element e = r*64 + lane).
-// Each batch of 64 keys (one per lane) is skipped when no key beats the
-// current k-th best; otherwise it is bitonic-sorted across the wave, reversed
-// and min-merged into the list's last register, and a bitonic merge restores
-// the order.  A query with several tiles writes each tile's k best to the
-// workspace; the last tile to finish merges them with the same routine.
+// One 256-thread workgroup per tile of up to TOPK_TILE candidates (16 keys
+// per thread, element e = j*256 + thread):
+//   1. every thread takes the minimum of its keys; the k-th smallest of these
+//      256 minima (found by one wave with a bitwise radix search on ballots)
+//      is a threshold T with at least k keys <= T (the k minima themselves),
+//      and for unordered costs only slightly more than k;
+//   2. keys <= T are compacted into LDS with one atomic per wave and key slot;
+//   3. each compacted key is placed by counting the compacted keys below it;
+//      keys placed at rank < k are the k best, already in order.
+// If more than 1024 keys pass the threshold (only possible for k > 64), a
+// workgroup-wide bitwise radix search over them takes the place of step 3.
+// A query with several tiles writes each tile's sorted k best to the
+// workspace; the last tile to finish selects again over those lists.
 #include "cm_internal.h"
 
 namespace cm {
 namespace {
 
 constexpr uint64_t SENT = ~0ull;  // empty slot: ranks after every real key
+constexpr int TK_THREADS = 256;
+constexpr int TK_WAVES = TK_THREADS / 64;
+constexpr int TK_PER = TOPK_TILE / TK_THREADS;
+constexpr int RANK_MAX = 1024;  // largest compacted set placed by counting
+static_assert(TK_PER * TK_THREADS == TOPK_TILE, "tile split");
+static_assert(TOPK_TILE > CM_MAX_K, "a merge pass must make progress");
+static_assert(TK_THREADS >= CM_MAX_K, "one thread per output slot");
 
 __device__ inline uint64_t make_key(float c, uint32_t idx)
 {
     uint32_t b = __float_as_uint(c);
     const uint32_t mag = b & 0x7fffffffu;
-    if (mag == 0) b = 0;                        // -0 -> +0
+    if (mag == 0) b = 0;                          // -0 -> +0
     else if (mag > 0x7f800000u) b = 0x7fc00000u;  // any NaN -> one quiet NaN
     b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
     return ((uint64_t)b << 32) | idx;
 }
 
-__device__ inline uint64_t shfl_xor64(uint64_t v, int m)
-{
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ inline uint64_t shfl64(uint64_t v, int src)
-{
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ inline uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
-
-template <int M>
-struct Beam {
-    uint64_t R[M];
-
-    __device__ void clear()
-    {
-#pragma unroll
-        for (int r = 0; r < M; ++r) R[r] = SENT;
-    }
-
-    // element e = k-1 of the sorted list, broadcast to the wave
-    __device__ uint64_t kth(int k) const
-    {
-        const int e = k - 1;
-        const int rr = e >> 6;
-        uint64_t v = R[0];
-#pragma unroll
-        for (int r = 1; r < M; ++r)
-            if (r == rr) v = R[r];
-        return shfl64(v, e & 63);
-    }
-
-    __device__ void insert(uint64_t key, int lane)
-    {
-        // bitonic sort of the 64 incoming keys, ascending
-#pragma unroll
-        for (int kk = 2; kk <= 64; kk <<= 1) {
-#pragma unroll
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                const uint64_t o = shfl_xor64(key, j);
-                const bool asc = (lane & kk) == 0;
-                const bool low = (lane & j) == 0;
-                key = (low == asc) ? umin64(key, o) : umax64(key, o);
-            }
-        }
-        // the smallest 64*M of list + batch form a bitonic sequence
-        R[M - 1] = umin64(R[M - 1], shfl64(key, 63 - lane));
-#pragma unroll
-        for (int j = 32 * M; j >= 64; j >>= 1) {
-            const int d = j >> 6;
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                if ((r & d) == 0) {
-                    const uint64_t a = R[r], b = R[r | d];
-                    R[r] = umin64(a, b);
-                    R[r | d] = umax64(a, b);
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 32; j > 0; j >>= 1) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                const uint64_t o = shfl_xor64(R[r], j);
-                R[r] = ((lane & j) == 0) ? umin64(R[r], o) : umax64(R[r], o);
-            }
-        }
-    }
-
-    // stream keys src[0..n) through the list
-    __device__ void absorb(const uint64_t *src, int n, int k, int lane)
-    {
-        uint64_t thr = kth(k);
-        for (int base = 0; base < n; base += 64) {
-            const int e = base + lane;
-            const uint64_t key = e < n ? src[e] : SENT;
-            if (!__any(key < thr)) continue;
-            insert(key, lane);
-            thr = kth(k);
-        }
-    }
+struct TopkShared {
+    uint64_t mins[TK_THREADS];
+    uint64_t filt[TOPK_TILE];
+    uint64_t best[CM_MAX_K];
+    uint64_t thr;
+    uint32_t nfilt;
+    uint32_t cnt[2][TK_WAVES];
+    uint32_t red_and[TK_WAVES], red_or[TK_WAVES];
 };
+
+__device__ inline uint32_t wave_count(bool p) { return (uint32_t)__popcll(__ballot(p)); }
+
+// ---------------------------------------------------------------- one wave
+// The value v such that the rank-th (1-based) smallest selected value is v;
+// rank becomes the rank among the selected values equal to v.
+template <int NV>
+__device__ uint32_t wave_radix(const uint32_t (&val)[NV], const bool (&sel)[NV], uint32_t &rank)
+{
+    uint32_t a = 0xffffffffu, o = 0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        if (sel[j]) {
+            a &= val[j];
+            o |= val[j];
+        }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        a &= (uint32_t)__shfl_xor((int)a, d);
+        o |= (uint32_t)__shfl_xor((int)o, d);
+    }
+    const uint32_t diff = a ^ o;
+    if (diff == 0) return a;
+    const int hb = 31 - __clz(diff);
+    uint32_t prefix = a & ~((2u << hb) - 1u);  // bits above hb are shared
+    for (int b = hb; b >= 0; --b) {
+        const uint32_t hmask = ~((2u << b) - 1u);
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            c += wave_count(sel[j] && ((val[j] ^ prefix) & hmask) == 0 && !((val[j] >> b) & 1u));
+        if (c < rank) {
+            rank -= c;
+            prefix |= 1u << b;
+        }
+    }
+    return prefix;
+}
+
+// Threshold with exactly `rank` selected keys <= it (1-based rank, at least
+// `rank` keys selected): the rank-th smallest key, or the largest possible
+// key with the same cost image when all keys tying there are needed.
+template <int NV>
+__device__ uint64_t wave_threshold(const uint64_t (&key)[NV], uint32_t rank)
+{
+    uint32_t hi[NV], lo[NV];
+    bool sel[NV], eq[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        hi[j] = (uint32_t)(key[j] >> 32);
+        lo[j] = (uint32_t)key[j];
+        sel[j] = key[j] != SENT;
+    }
+    const uint32_t thi = wave_radix(hi, sel, rank);
+    uint32_t neq = 0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        eq[j] = sel[j] && hi[j] == thi;
+        neq += wave_count(eq[j]);
+    }
+    const uint32_t tlo = neq > rank ? wave_radix(lo, eq, rank) : 0xffffffffu;
+    return ((uint64_t)thi << 32) | tlo;
+}
+
+// ---------------------------------------------------------------- workgroup
+__device__ inline uint32_t block_sum(uint32_t wave_value, TopkShared &sh, int &buf)
+{
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh.cnt[buf][w] = wave_value;
+    __syncthreads();
+    uint32_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < TK_WAVES; ++j) tot += sh.cnt[buf][j];
+    buf ^= 1;
+    return tot;
+}
+
+__device__ uint32_t block_radix(const uint32_t (&val)[TK_PER], const bool (&sel)[TK_PER],
+                                uint32_t &rank, TopkShared &sh, int &buf)
+{
+    uint32_t a = 0xffffffffu, o = 0;
+#pragma unroll
+    for (int j = 0; j < TK_PER; ++j)
+        if (sel[j]) {
+            a &= val[j];
+            o |= val[j];
+        }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        a &= (uint32_t)__shfl_xor((int)a, d);
+        o |= (uint32_t)__shfl_xor((int)o, d);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh.red_and[w] = a;
+        sh.red_or[w] = o;
+    }
+    __syncthreads();
+    a = 0xffffffffu;
+    o = 0;
+#pragma unroll
+    for (int j = 0; j < TK_WAVES; ++j) {
+        a &= sh.red_and[j];
+        o |= sh.red_or[j];
+    }
+    __syncthreads();
+    const uint32_t diff = a ^ o;
+    if (diff == 0) return a;
+    const int hb = 31 - __clz(diff);
+    uint32_t prefix = a & ~((2u << hb) - 1u);
+    for (int b = hb; b >= 0; --b) {
+        const uint32_t hmask = ~((2u << b) - 1u);
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < TK_PER; ++j)
+            c += wave_count(sel[j] && ((val[j] ^ prefix) & hmask) == 0 && !((val[j] >> b) & 1u));
+        const uint32_t cnt = block_sum(c, sh, buf);
+        if (cnt < rank) {
+            rank -= cnt;
+            prefix |= 1u << b;
+        }
+    }
+    return prefix;
+}
+
+// Threshold over the compacted keys when too many passed to place by counting.
+__device__ uint64_t block_threshold(int nf, uint32_t rank, TopkShared &sh)
+{
+    int buf = 0;
+    uint32_t hi[TK_PER], lo[TK_PER];
+    bool sel[TK_PER], eq[TK_PER];
+#pragma unroll
+    for (int j = 0; j < TK_PER; ++j) {
+        const int e = j * TK_THREADS + (int)threadIdx.x;
+        const uint64_t key = e < nf ? sh.filt[e] : SENT;
+        hi[j] = (uint32_t)(key >> 32);
+        lo[j] = (uint32_t)key;
+        sel[j] = key != SENT;
+    }
+    const uint32_t thi = block_radix(hi, sel, rank, sh, buf);
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < TK_PER; ++j) {
+        eq[j] = sel[j] && hi[j] == thi;
+        c += wave_count(eq[j]);
+    }
+    const uint32_t neq = block_sum(c, sh, buf);
+    const uint32_t tlo = neq > rank ? block_radix(lo, eq, rank, sh, buf) : 0xffffffffu;
+    return ((uint64_t)thi << 32) | tlo;
+}
+
+// Select the k smallest keys of the workgroup (element e = j*256 + thread;
+// the nvalid real keys occupy elements 0..nvalid-1, the rest are SENT) into
+// sh.best, ascending.  Returns min(k, nvalid).
+__device__ int tile_select(const uint64_t (&key)[TK_PER], int nvalid, int k, TopkShared &sh)
+{
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    if (t == 0) sh.nfilt = 0;
+    uint64_t T = SENT - 1;  // at most k keys: all of them
+    if (nvalid > k) {
+        uint64_t m = key[0];
+#pragma unroll
+        for (int j = 1; j < TK_PER; ++j) m = key[j] < m ? key[j] : m;
+        sh.mins[t] = m;
+        __syncthreads();
+        if (t < 64) {
+            uint64_t v[TK_THREADS / 64];
+#pragma unroll
+            for (int j = 0; j < TK_THREADS / 64; ++j) v[j] = sh.mins[j * 64 + lane];
+            // min(nvalid, 256) >= k + 1 threads hold a real key
+            const uint64_t thr = wave_threshold(v, (uint32_t)k);
+            if (t == 0) sh.thr = thr;
+        }
+    }
+    __syncthreads();
+    if (nvalid > k) T = sh.thr;
+    // compact the keys <= T
+#pragma unroll
+    for (int j = 0; j < TK_PER; ++j) {
+        const bool p = key[j] <= T && key[j] != SENT;
+        const uint64_t mask = __ballot(p);
+        if (mask) {
+            const int first = __ffsll((unsigned long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane == first) base = atomicAdd(&sh.nfilt, (uint32_t)__popcll(mask));
+            base = (uint32_t)__shfl((int)base, first);
+            if (p) {
+                const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                sh.filt[base + below] = key[j];
+            }
+        }
+    }
+    __syncthreads();
+    const int nf = (int)sh.nfilt;
+    if (nf > RANK_MAX) {
+        // many ties at the threshold's cost: exact threshold over the compacted set
+        const uint64_t T2 = block_threshold(nf, (uint32_t)k, sh);
+        __syncthreads();
+        if (t == 0) sh.nfilt = 0;
+        __syncthreads();
+        uint64_t mine[TK_PER];
+#pragma unroll
+        for (int j = 0; j < TK_PER; ++j) {
+            const int e = j * TK_THREADS + t;
+            mine[j] = e < nf ? sh.filt[e] : SENT;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < TK_PER; ++j)
+            if (mine[j] <= T2 && mine[j] != SENT) sh.filt[atomicAdd(&sh.nfilt, 1u)] = mine[j];
+        __syncthreads();
+    }
+    const int n = min((int)sh.nfilt, RANK_MAX);
+    // place by counting; ranks >= k are dropped
+    for (int e = t; e < n; e += TK_THREADS) {
+        const uint64_t mine = sh.filt[e];
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += sh.filt[j] < mine;
+        if (r < k) sh.best[r] = mine;
+    }
+    __syncthreads();
+    return min(n, k);
+}
 
 __device__ inline int find_tile_query(const TopkLaunch &L, int t)
 {
@@ -128,14 +285,15 @@ __device__ inline int find_tile_query(const TopkLaunch &L, int t)
     return q;
 }
 
-template <int M>
-__global__ __launch_bounds__(64) void k_topk(TopkLaunch L, const float *__restrict__ cost,
-                                             uint64_t *__restrict__ tpart,
-                                             int32_t *__restrict__ tcnt,
-                                             int32_t *__restrict__ idx_out,
-                                             float *__restrict__ val_out)
+__global__ __launch_bounds__(TK_THREADS) void k_topk(TopkLaunch L, const float *__restrict__ cost,
+                                                     uint64_t *__restrict__ tpart,
+                                                     int32_t *__restrict__ tcnt,
+                                                     int32_t *__restrict__ idx_out,
+                                                     float *__restrict__ val_out)
 {
-    const int lane = threadIdx.x;
+    __shared__ TopkShared sh;
+    __shared__ int last;
+    const int t = threadIdx.x;
     const int task = blockIdx.x;
     const int q = find_tile_query(L, task);
     const TopkQ Q = L.q[q];
@@ -143,51 +301,59 @@ __global__ __launch_bounds__(64) void k_topk(TopkLaunch L, const float *__restri
     const int k = L.k;
     const float *c = cost + Q.cost_off;
 
-    Beam<M> B;
-    B.clear();
     const int beg = tile * TOPK_TILE;
-    const int end = min(Q.N, beg + TOPK_TILE);
-    uint64_t thr = SENT;
-    for (int base = beg; base < end; base += 64) {
-        const int i = base + lane;
-        const uint64_t key = i < end ? make_key(c[i], (uint32_t)i) : SENT;
-        if (!__any(key < thr)) continue;
-        B.insert(key, lane);
-        thr = B.kth(k);
+    const int nvalid = max(0, min(TOPK_TILE, Q.N - beg));
+    uint64_t key[TK_PER];
+#pragma unroll
+    for (int j = 0; j < TK_PER; ++j) {
+        const int e = j * TK_THREADS + t;
+        key[j] = e < nvalid ? make_key(c[beg + e], (uint32_t)(beg + e)) : SENT;
     }
+    int nbest = tile_select(key, nvalid, k, sh);
 
     if (Q.ntiles > 1) {
         uint64_t *mine = tpart + (int64_t)task * k;
+        if (t < k) mine[t] = t < nbest ? sh.best[t] : SENT;
+        __threadfence();
+        __syncthreads();
+        if (t == 0) last = atomicAdd(&tcnt[q], 1) == Q.ntiles - 1;
+        __syncthreads();
+        if (!last) return;
+        __threadfence();
+        // merge the tiles' lists: every list but the last is full, so the
+        // real keys are the first total_valid entries
+        const uint64_t *src = tpart + (int64_t)Q.tile0 * k;
+        const int total = Q.ntiles * k;
+        const int total_valid = (Q.ntiles - 1) * k + min(k, Q.N - (Q.ntiles - 1) * TOPK_TILE);
+        const int fresh = TOPK_TILE - k;
+        nbest = 0;
+        for (int base = 0; base < total; base += fresh) {
+            const int nnew = max(0, min(fresh, total_valid - base));
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int e = r * 64 + lane;
-            if (e < k) mine[e] = B.R[r];
+            for (int j = 0; j < TK_PER; ++j) {
+                const int e = j * TK_THREADS + t;
+                if (e < nbest)
+                    key[j] = sh.best[e];
+                else if (e < nbest + nnew)
+                    key[j] = src[base + e - nbest];
+                else
+                    key[j] = SENT;
+            }
+            __syncthreads();
+            nbest = tile_select(key, nbest + nnew, k, sh);
         }
-        __threadfence();
-        int old = 0;
-        if (lane == 0) old = atomicAdd(&tcnt[q], 1);
-        old = __shfl(old, 0);
-        if (old != Q.ntiles - 1) return;
-        __threadfence();
-        B.clear();
-        B.absorb(tpart + (int64_t)Q.tile0 * k, Q.ntiles * k, k, lane);
-        if (lane == 0) atomicExch(&tcnt[q], 0);
+        if (t == 0) atomicExch(&tcnt[q], 0);
     }
 
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-        const int e = r * 64 + lane;
-        if (e < k) {
-            const uint64_t key = B.R[r];
-            int32_t id = -1;
-            float v = __builtin_inff();
-            if (key != SENT) {
-                id = (int32_t)(uint32_t)key;
-                v = c[id];
-            }
-            idx_out[(int64_t)Q.out_q * k + e] = id;
-            val_out[(int64_t)Q.out_q * k + e] = v;
+    if (t < k) {
+        int32_t id = -1;
+        float v = __builtin_inff();
+        if (t < nbest) {
+            id = (int32_t)(uint32_t)sh.best[t];
+            v = c[id];
         }
+        idx_out[(int64_t)Q.out_q * k + t] = id;
+        val_out[(int64_t)Q.out_q * k + t] = v;
     }
 }
 
@@ -197,15 +363,8 @@ hipError_t launch_topk(const TopkLaunch &L, const float *cost, uint64_t *tpart, 
                        int32_t *idx_out, float *val_out, hipStream_t st)
 {
     if (L.ntasks == 0) return hipSuccess;
-    if (L.k <= 64)
-        hipLaunchKernelGGL(k_topk<1>, dim3(L.ntasks), dim3(64), 0, st, L, cost, tpart, tcnt,
-                           idx_out, val_out);
-    else if (L.k <= 128)
-        hipLaunchKernelGGL(k_topk<2>, dim3(L.ntasks), dim3(64), 0, st, L, cost, tpart, tcnt,
-                           idx_out, val_out);
-    else
-        hipLaunchKernelGGL(k_topk<4>, dim3(L.ntasks), dim3(64), 0, st, L, cost, tpart, tcnt,
-                           idx_out, val_out);
+    hipLaunchKernelGGL(k_topk, dim3(L.ntasks), dim3(TK_THREADS), 0, st, L, cost, tpart, tcnt,
+                       idx_out, val_out);
     return hipGetLastError();
 }
 
