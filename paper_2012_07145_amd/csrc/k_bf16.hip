@@ -30,6 +30,8 @@
 namespace cm {
 namespace {
 
+constexpr int USTAGE = 16;  // hoisted rows staged in LDS per refill
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -47,7 +49,7 @@ __device__ inline uint32_t pack_bf16x2(float a, float b)
 __device__ inline bf16x2 pair_reg(uint32_t bits)
 {
     uint32_t v;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "i"(bits));
+    asm volatile("s_mov_b32 %0, %1" : "=s"(v) : "i"(bits));
     return __builtin_bit_cast(bf16x2, v);
 }
 
@@ -156,13 +158,85 @@ __device__ inline void load_stage(StageIn &in, const char *xs, const char *ts, u
     in.t = *reinterpret_cast<const float4 *>(ts + to);
 }
 
+struct Weights {
+    bf16x8 A1h[3], A1l[3], A2h[2], A2l[2];
+    float b2v[4];
+};
+
+// Refill this wave's LDS slice with the hoisted rows of stages s .. s+n-1.
+// Only this wave reads its slice and its LDS operations complete in order.
+__device__ inline void refill_u(float4 *ur, const float4 *ug, int s, int n, int lane)
+{
+    const int nv = n * (H / 4);
+    for (int v = lane; v < nv; v += 64) ur[v] = ug[(int64_t)s * (H / 4) + v];
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One stage of 32 candidates: both dense layers on the matrix cores, the
+// coefficient dot product with the cost terms, and the compensated sum.
+__device__ __forceinline__ void stage_math(const StageIn &in, const float4 *us, int hf,
+                                           const Weights &w, const Pairs &kp, float &sum,
+                                           float &comp)
+{
+    // first layer: accumulator starts from U[s]; register g*4+j holds
+    // hidden unit g*8 + hf*4 + j
+    f32x16 acc;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 u4 = us[g * 2 + hf];
+        acc[g * 4 + 0] = u4.x;
+        acc[g * 4 + 1] = u4.y;
+        acc[g * 4 + 2] = u4.z;
+        acc[g * 4 + 3] = u4.w;
+    }
+    bf16x8 bh, bl;
+    log_split(in.x0, bh, bl, kp);
+    acc = mfma(w.A1h[0], bh, acc);
+    acc = mfma(w.A1l[0], bh, acc);
+    acc = mfma(w.A1h[0], bl, acc);
+    log_split(in.x1, bh, bl, kp);
+    acc = mfma(w.A1h[1], bh, acc);
+    acc = mfma(w.A1l[1], bh, acc);
+    acc = mfma(w.A1h[1], bl, acc);
+    log_split4(in.x2, bh, bl, kp);
+    acc = mfma(w.A1h[2], bh, acc);
+    acc = mfma(w.A1l[2], bh, acc);
+    acc = mfma(w.A1h[2], bl, acc);
+
+    // coefficient layer (output registers 0..3 are the 8 real outputs); its
+    // bias is added after the products
+    f32x16 acc2;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        uint32_t hh[4], hl[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            split2(relu(acc[t * 8 + 2 * d]), relu(acc[t * 8 + 2 * d + 1]), hh[d], hl[d], kp);
+        const bf16x8 Hh = __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
+        const bf16x8 Hl = __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
+        acc2 = mfma(w.A2h[t], Hh, acc2);
+        acc2 = mfma(w.A2l[t], Hh, acc2);
+        acc2 = mfma(w.A2h[t], Hl, acc2);
+    }
+    // lanes hf=0 hold coefficients 0..3 of their candidate, hf=1 hold 4..7
+    float v = relu(acc2[0] + w.b2v[0]) * in.t.x;
+    v = fmaf(relu(acc2[1] + w.b2v[1]), in.t.y, v);
+    v = fmaf(relu(acc2[2] + w.b2v[2]), in.t.z, v);
+    v = fmaf(relu(acc2[3] + w.b2v[3]), in.t.w, v);
+    kahan_add(sum, comp, add_halves(v));
+}
+
 __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_eval_bf16(
-    EvalLaunch L, const Bf16Pack *__restrict__ pk, const uint16_t *__restrict__ sched,
-    const float *__restrict__ terms, const float *__restrict__ U, float *__restrict__ cost)
+    EvalLaunch L, const Bf16Pack *__restrict__ pk, const uint16_t *sched, const float *terms,
+    const float *__restrict__ U, float *__restrict__ cost)
 {
     __shared__ float2 lds_part[EVAL_WAVES][TILE_ROWS];
+    __shared__ float4 lds_u[EVAL_WAVES][USTAGE * H / 4];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform values are kept in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = find_task_query(L, blockIdx.x);
     const EvalQ Q = L.q[q];
     const int P = Q.parts;
@@ -180,20 +254,19 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
     const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
 
-    bf16x8 A1h[3], A1l[3], A2h[2], A2l[2];
+    Weights w;
 #pragma unroll
     for (int st = 0; st < 3; ++st) {
-        A1h[st] = __builtin_bit_cast(bf16x8, pk->a1[0][st][lane]);
-        A1l[st] = __builtin_bit_cast(bf16x8, pk->a1[1][st][lane]);
+        w.A1h[st] = __builtin_bit_cast(bf16x8, pk->a1[0][st][lane]);
+        w.A1l[st] = __builtin_bit_cast(bf16x8, pk->a1[1][st][lane]);
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        A2h[t] = __builtin_bit_cast(bf16x8, pk->a2[0][t][lane]);
-        A2l[t] = __builtin_bit_cast(bf16x8, pk->a2[1][t][lane]);
+        w.A2h[t] = __builtin_bit_cast(bf16x8, pk->a2[0][t][lane]);
+        w.A2l[t] = __builtin_bit_cast(bf16x8, pk->a2[1][t][lane]);
     }
-    float b2v[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) b2v[r] = pk->b2[hf * 4 + r];
+    for (int r = 0; r < 4; ++r) w.b2v[r] = pk->b2[hf * 4 + r];
     const Pairs kp = make_pairs();
 
     // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart
@@ -204,83 +277,37 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     const uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
     const uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
     const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
-    const float4 *urow = reinterpret_cast<const float4 *>(U + Q.u_off + (int64_t)s0 * H);
+    const float4 *ug = reinterpret_cast<const float4 *>(U + Q.u_off);
+    // this wave's slice of LDS holds the hoisted rows of up to USTAGE stages
+    float4 *ur = lds_u[wave];
 
     float sum = 0.f, comp = 0.f;
     if (s0 < s1) {
-        StageIn cur, nxt;
-        load_stage(cur, xs, ts, xo, x2o, to);
-        for (int s = s0; s < s1; ++s) {
-            // prefetch the next stage; the last iteration re-reads its own
-            // stage (cache-resident) so that every iteration issues the same loads
+        // two register buffers alternate so that a stage's loads stay in
+        // flight during the previous stage's arithmetic without copies
+        StageIn A, B;
+        load_stage(A, xs, ts, xo, x2o, to);
+        for (int s = s0; s < s1; s += 2) {
+            if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
             if (s + 1 < s1) {
                 xs += xstep;
                 ts += tstep;
             }
-            load_stage(nxt, xs, ts, xo, x2o, to);
+            load_stage(B, xs, ts, xo, x2o, to);
+            // keep the loads here, ahead of their use (sched and terms are not
+            // restrict-qualified, so the compiler cannot move them across this)
+            asm volatile("" ::: "memory");
+            stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            if (s + 1 >= s1) break;
 
-            // first layer: accumulator starts from U[s]; register g*4+j holds
-            // hidden unit g*8 + hf*4 + j
-            f32x16 acc;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const float4 u4 = urow[g * 2 + hf];
-                acc[g * 4 + 0] = u4.x;
-                acc[g * 4 + 1] = u4.y;
-                acc[g * 4 + 2] = u4.z;
-                acc[g * 4 + 3] = u4.w;
+            if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
+            if (s + 2 < s1) {
+                xs += xstep;
+                ts += tstep;
             }
-            urow += H / 4;
-            bf16x8 bh, bl;
-            log_split(cur.x0, bh, bl, kp);
-            acc = mfma(A1h[0], bh, acc);
-            acc = mfma(A1l[0], bh, acc);
-            acc = mfma(A1h[0], bl, acc);
-            log_split(cur.x1, bh, bl, kp);
-            acc = mfma(A1h[1], bh, acc);
-            acc = mfma(A1l[1], bh, acc);
-            acc = mfma(A1h[1], bl, acc);
-            log_split4(cur.x2, bh, bl, kp);
-            acc = mfma(A1h[2], bh, acc);
-            acc = mfma(A1l[2], bh, acc);
-            acc = mfma(A1h[2], bl, acc);
-
-            // coefficient layer (output registers 0..3 are the 8 real
-            // outputs); its bias is added after the products
-            f32x16 acc2;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                uint32_t hh[4], hl[4];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const float a = relu(acc[t * 8 + 2 * d]);
-                    const float b = relu(acc[t * 8 + 2 * d + 1]);
-                    split2(a, b, hh[d], hl[d], kp);
-                }
-                const bf16x8 Hh =
-                    __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
-                const bf16x8 Hl =
-                    __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
-                acc2 = mfma(A2h[t], Hh, acc2);
-                acc2 = mfma(A2l[t], Hh, acc2);
-                acc2 = mfma(A2h[t], Hl, acc2);
-            }
-            // lanes hf=0 hold coefficients 0..3 of their candidate, hf=1 hold 4..7
-            float v = relu(acc2[0] + b2v[0]) * cur.t.x;
-            v = fmaf(relu(acc2[1] + b2v[1]), cur.t.y, v);
-            v = fmaf(relu(acc2[2] + b2v[2]), cur.t.z, v);
-            v = fmaf(relu(acc2[3] + b2v[3]), cur.t.w, v);
-            kahan_add(sum, comp, add_halves(v));
-            // the next stage's loads were issued before this stage's
-            // arithmetic; pin them to this iteration so the compiler cannot
-            // sink them into the iteration that consumes them
-            asm volatile("" : "+v"(nxt.x0.x), "+v"(nxt.x0.y), "+v"(nxt.x0.z), "+v"(nxt.x0.w),
-                         "+v"(nxt.x1.x), "+v"(nxt.x1.y), "+v"(nxt.x1.z), "+v"(nxt.x1.w),
-                         "+v"(nxt.x2.x), "+v"(nxt.x2.y), "+v"(nxt.t.x), "+v"(nxt.t.y),
-                         "+v"(nxt.t.z), "+v"(nxt.t.w));
-            cur = nxt;
+            load_stage(A, xs, ts, xo, x2o, to);
+            asm volatile("" ::: "memory");
+            stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
         }
     }
 
