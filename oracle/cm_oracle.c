@@ -22,6 +22,8 @@
  *    be zero);
  *  - there is no activation after the embeddings;
  *  - "positive weights" are produced by a ReLU, so exact zeros are allowed;
+ *    the ReLU lets a NaN through (as the usual ML-framework ReLU does), so an
+ *    invalid feature gives a NaN cost instead of a silently finite one;
  *  - every layer has a bias;
  *  - the algorithm-specific features are one vector per (query, stage),
  *    shared by all candidates of the query;
@@ -101,13 +103,13 @@ static double stage_eval(const cmo_params *P, const float *pipe_s,
     for (int j = 0; j < H; ++j) {
         double a = (double)P->b1[j];
         for (int k = 0; k < 2 * E; ++k) a += (double)P->W1[j * 2 * E + k] * z[k];
-        h[j] = a > 0.0 ? a : 0.0;
+        h[j] = a < 0.0 ? 0.0 : a; /* ReLU; a NaN passes through */
     }
     /* output layer with ReLU: the non-negative coefficients */
     for (int m = 0; m < C; ++m) {
         double a = (double)P->b2[m];
         for (int j = 0; j < H; ++j) a += (double)P->W2[m * H + j] * h[j];
-        c[m] = a > 0.0 ? a : 0.0;
+        c[m] = a < 0.0 ? 0.0 : a;
     }
     /* coefficients weight the hand-derived cost terms (App. B) */
     double v = 0.0;

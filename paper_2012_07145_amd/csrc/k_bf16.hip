@@ -108,8 +108,8 @@ __device__ inline void log_split4(uint2 raw, bf16x8 &hi, bf16x8 &lo, const Pairs
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
-// max(x, 0) on the bit pattern: negative floats are negative integers
-__device__ inline float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+// ReLU that lets a NaN through, like the oracle
+__device__ inline float relu(float x) { return x < 0.f ? 0.f : x; }
 
 __device__ inline void kahan_add(float &s, float &c, float v)
 {

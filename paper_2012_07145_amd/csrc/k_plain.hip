@@ -102,7 +102,7 @@ __global__ __launch_bounds__(64) void k_eval_fp32(EvalLaunch L, const float *__r
             float a = u[j];
 #pragma unroll
             for (int e = 0; e < E; ++e) a = fmaf(W1[j * 2 * E + E + e], es[e], a);
-            h[j] = a > 0.f ? a : 0.f;
+            h[j] = a < 0.f ? 0.f : a;  // ReLU; a NaN passes through
         }
         const float *tr = terms + Q.terms_off + r * C;
         float v = 0.f;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64) void k_eval_fp32(EvalLaunch L, const float *__r
             float a = b2[m];
 #pragma unroll
             for (int j = 0; j < H; ++j) a = fmaf(W2[m * H + j], h[j], a);
-            const float c = a > 0.f ? a : 0.f;
+            const float c = a < 0.f ? 0.f : a;
             v = fmaf(c, tr[m], v);
         }
         // Kahan-compensated stage sum

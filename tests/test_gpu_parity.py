@@ -273,3 +273,32 @@ def test_hoist_then_eval_equals_eval_batch(cm, model, prec):
     torch.cuda.synchronize()
     assert torch.equal(cost_a, cost_b)
     ws.close()
+
+
+def test_negative_and_signed_zero_features(cm, oracle_mod, model, params):
+    # log1p is defined above -1: a feature in (-1, 0) and a -0 follow the
+    # oracle in both forms; a feature below -1 makes the candidate's cost NaN
+    q = draw_query(np.random.default_rng(60), 9, 70)
+    sched = q.sched.copy()
+    sched[3, 5, 7] = -0.5
+    sched[6, 9, 33] = -0.0
+    sched[2, 11, 1] = -3.0
+    q2 = Query(q.pipe, sched, q.terms)
+    ok = np.ones(70, bool)
+    ok[11] = False
+    for prec, tol in (("fp32", FP32_TOL), ("bf16", BF16_TOL)):
+        (c,), _, _ = gc.gpu_costs(cm, model, [q2], prec)
+        assert np.isnan(c[11]), prec
+        qq = q2 if prec == "fp32" else gc.quantized(q2)
+        ref = oracle_mod.eval_query(params, qq.pipe, qq.sched, qq.terms)
+        assert np.isnan(ref[11])
+        assert gc.rel_err(c[ok], ref[ok]).max() <= tol, prec
+
+
+def test_bf16_long_query_reads_hoisted_rows_from_memory(cm, oracle_mod, model, params):
+    # more stages than the evaluator keeps in LDS
+    q = draw_query(np.random.default_rng(61), 300, 40)
+    (c,), _, _ = gc.gpu_costs(cm, model, [q], "bf16")
+    qq = gc.quantized(q)
+    ref = oracle_mod.eval_query(params, qq.pipe, qq.sched, qq.terms)
+    assert gc.rel_err(c, ref).max() <= BF16_TOL

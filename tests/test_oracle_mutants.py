@@ -29,13 +29,14 @@ PIN_TESTS = [
     pins.test_select_signed_zero_tie,
     pins.test_select_nan_last_and_padding,
     pins.test_select_brute_force_tiny,
+    pins.test_relu_clips_negative_and_passes_nan,
 ]
 
 # (name, text in cm_oracle.c, replacement)
 MUTANTS = [
     ("stack order swapped", "z[E + e] = a;", "z[e] = a; z[E + e] = z[E + e];"),
-    ("no hidden ReLU", "h[j] = a > 0.0 ? a : 0.0;", "h[j] = a;"),
-    ("no output ReLU", "c[m] = a > 0.0 ? a : 0.0;", "c[m] = a;"),
+    ("no hidden ReLU", "h[j] = a < 0.0 ? 0.0 : a;", "h[j] = a;"),
+    ("no output ReLU", "c[m] = a < 0.0 ? 0.0 : a;", "c[m] = a;"),
     ("log instead of log1p", "x[f] = log1p((double)sched_si[f]);",
      "x[f] = log((double)sched_si[f] + 1e-300);"),
     ("pipeline features not logged", "p[f] = log1p((double)pipe_s[f]);",
@@ -51,6 +52,7 @@ MUTANTS = [
      "return (A->idx < B->idx) - (A->idx > B->idx);"),
     ("NaN first", "return A->nan - B->nan;", "return B->nan - A->nan;"),
     ("padding index 0", "idx_out[j] = -1;", "idx_out[j] = 0;"),
+    ("ReLU maps NaN to 0", "h[j] = a < 0.0 ? 0.0 : a;", "h[j] = a > 0.0 ? a : 0.0;"),
     ("descending order", "if (A->key < B->key) return -1;", "if (A->key > B->key) return -1;"),
 ]
 

@@ -240,3 +240,20 @@ def test_select_brute_force_tiny(oracle_mod):
                    key=lambda seq: [cc.key_tuple(cost[i], i) for i in seq])
         assert idx[:kk].tolist() == list(best), (cost, k, idx)
         assert np.all(idx[kk:] == -1)
+
+
+def test_relu_clips_negative_and_passes_nan(oracle_mod):
+    # feature x routed straight to coefficient 0: cost = ReLU(log1p(x)).
+    # x = -0.5 gives log1p = -ln 2 < 0, clipped to 0; x = 1 gives ln 2; a NaN
+    # feature (or x < -1) gives a NaN cost rather than a silently finite one.
+    params = cc.log_params("sched")
+    xs = np.array([-0.5, 1.0, np.nan, -3.0], np.float32)
+    pipe = np.zeros((1, 56), np.float32)
+    sched = np.zeros((1, 4, 40), np.float32)
+    sched[0, :, 0] = xs
+    terms = np.zeros((1, 4, 8), np.float32)
+    terms[0, :, 0] = 1.0
+    cost = oracle_mod.eval_query(params, pipe, sched, terms)
+    assert cost[0] == 0.0
+    assert abs(cost[1] - math.log(2.0)) <= 1e-15
+    assert np.isnan(cost[2]) and np.isnan(cost[3])
