@@ -50,6 +50,7 @@ extern "C" {
 #define CM_N_PARAMS 4184     /* float32 parameters, layout in cm_model_create */
 #define CM_MAX_K 256         /* largest beam width of cm_topk_per_query */
 #define CM_STAGE_CHUNK 16    /* sets the stage split of CM_BF16 (see cm_eval_batch) */
+#define CM_STEP_MAX_QUERIES 256 /* queries per cm_step_run */
 
 typedef int32_t cm_status;
 enum {
@@ -204,6 +205,218 @@ cm_status cm_eval_hoisted(const cm_model *model, cm_precision precision,
 cm_status cm_topk_per_query(const float *cost, const cm_batch *batch, int32_t k,
                             cm_workspace *ws, int32_t *idx_out, float *val_out,
                             cm_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Persistent beam step: hoist + evaluate + select for a ragged batch in one
+ * persistent launch that is replayed as a HIP graph.
+ *
+ * A step object owns device descriptors, control words and selection lists
+ * for `slots` steps that may be in flight at once.  cm_step_run writes the
+ * batch's descriptors into pinned host memory; the step then runs as
+ *   copy of the descriptors to the device -> hoist (only when U is NULL) ->
+ *   one persistent CM_BF16 evaluation kernel whose workgroups take tasks
+ *   from a device-wide queue, with each query's top-k selection run by the
+ *   workgroup that finishes the query's last task,
+ * either as one graph launch (captured once per slot and configuration) or
+ * as plain launches.  The launch shape depends only on the configuration,
+ * never on the batch.  Results are bit-identical to cm_eval_batch /
+ * cm_eval_hoisted (CM_BF16) followed by cm_topk_per_query, for every
+ * configuration.
+ * ------------------------------------------------------------------------ */
+typedef struct cm_step cm_step;
+
+typedef struct {
+    int32_t max_queries;  /* 1 .. CM_STEP_MAX_QUERIES */
+    int64_t max_stages;   /* sum over queries of n_stages */
+    int64_t max_cands;    /* sum over queries of n_cands */
+    int32_t max_k;        /* 1 .. CM_MAX_K */
+    int32_t slots;        /* 1 .. 8: steps in flight at once (descriptor sets) */
+} cm_step_desc;
+
+/* Launch configuration; none of it changes the results. */
+typedef struct {
+    int32_t grid;         /* persistent workgroups (8 waves each); 0 = two per
+                             compute unit */
+    int32_t group_tiles;  /* row-tile groups per task: 1, 2 or 4 (a group is
+                             8 / P tiles of 32 candidates) */
+    int32_t use_graph;    /* 1: replay a captured graph; 0: plain launches */
+} cm_step_config;
+
+/* Create a step on the current device for `model`, which must outlive it.
+ * Only CM_BF16 is supported (CM_EUNSUPPORTED otherwise).  Allocates device
+ * memory for the descriptors, control words, hoisted rows and selection
+ * lists of every slot, and pinned host memory for the descriptors.
+ * Errors: CM_EINVAL, CM_EUNSUPPORTED, CM_ENOMEM, CM_EDEVICE. */
+cm_status cm_step_create(const cm_model *model, cm_precision precision,
+                         const cm_step_desc *desc, cm_step **out);
+/* Waits for the step's work in flight, then frees everything it owns. */
+cm_status cm_step_destroy(cm_step *step);
+
+/* One beam step of every query of `batch` (layouts as for cm_eval_batch
+ * with CM_BF16; the batch's base pointers and every output pointer are
+ * device pointers):
+ *   - U: hoisted rows as cm_hoist_stages writes them for this batch, or
+ *     NULL to hoist inside the step (then pipe must be given);
+ *   - cost_out[cost_off + i]: every candidate's predicted runtime;
+ *   - idx_out[q*k + j], val_out[q*k + j]: query q's beam, as
+ *     cm_topk_per_query writes it.
+ * Asynchronous on `stream`.  The call waits on the host only when the slot
+ * it reuses is still in flight (more than `slots` steps queued).  Calls on
+ * one step are serialised; steps in flight on different streams use
+ * different slots.  Errors: CM_EINVAL, CM_E2BIG (capacity),
+ * CM_EDEVICE. */
+cm_status cm_step_run(cm_step *step, const cm_batch *batch, const float *U, int32_t k,
+                      float *cost_out, int32_t *idx_out, float *val_out, cm_stream stream);
+
+cm_status cm_step_set_config(cm_step *step, const cm_step_config *cfg);
+cm_status cm_step_get_config(const cm_step *step, cm_step_config *cfg);
+
+/* Autotuner: times every configuration of a built-in candidate set on this
+ * batch (`reps` timed runs each after one untimed run, median of HIP event
+ * times on `stream`), keeps the fastest as the step's configuration and
+ * returns it in *best (and its median time in microseconds in *best_us, if
+ * not NULL).  Synchronous.  The runs write the outputs like cm_step_run.
+ * Errors: as cm_step_run. */
+cm_status cm_step_autotune(cm_step *step, const cm_batch *batch, const float *U, int32_t k,
+                           float *cost_out, int32_t *idx_out, float *val_out, cm_stream stream,
+                           int32_t reps, cm_step_config *best, float *best_us);
+
+/* Kernel-only GPU time, in microseconds, of the step's most recent run (the
+ * persistent evaluation-and-selection kernel alone, without the descriptor
+ * copy or the hoist), from HIP events recorded around that kernel on the
+ * run's stream.  Waits for that run to finish.  Errors: CM_EINVAL,
+ * CM_ENOTFOUND (the step has not run), CM_EDEVICE. */
+cm_status cm_step_kernel_time(cm_step *step, float *us);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of beam-step queries from many concurrent
+ * search sessions (each session runs the beam search of Sec. 4 over one
+ * pipeline and submits one query per beam step).
+ *
+ * A server owns a worker thread, `max_slots` HIP streams each with a
+ * persistent step (above), and device pools for its sessions.  Requests are
+ * queued by cm_serve_submit and admitted by the worker in submission order
+ * as slots and memory free up: a request is admitted when a slot is free,
+ * the device bytes of the admitted, unfinished requests plus its own stay
+ * within `arena_bytes`, and its session has no other request in flight (a
+ * beam step depends on the previous one; later requests of such a session
+ * wait without blocking other sessions).  Each admission round launches the
+ * admitted requests as one micro-batch on a free slot's stream, so
+ * micro-batches on different slots overlap on the device.  Session state
+ * stays on the device: the hoisted rows of its stages (computed once, at
+ * open) and its latest beam.  Every result is the same as the request
+ * evaluated alone (cm_eval_batch CM_BF16 + cm_topk_per_query), bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct cm_server cm_server;
+
+typedef struct {
+    cm_precision precision;     /* CM_BF16 */
+    int32_t k;                  /* largest beam width of a request, 1 .. CM_MAX_K */
+    int64_t arena_bytes;        /* admission limit, see cm_serve_submit */
+    int32_t max_slots;          /* micro-batches in flight, 1 .. 8 */
+    int32_t max_pending;        /* queued, not yet admitted requests */
+    int32_t max_sessions;       /* open sessions */
+    int32_t max_stages;         /* stages of a session's pipeline */
+    int32_t max_batch_queries;  /* requests per micro-batch, 1 .. CM_STEP_MAX_QUERIES */
+    int64_t max_batch_cands;    /* candidates per micro-batch (and per request) */
+} cm_server_cfg;
+
+/* One beam step of a session: n_cands candidates over the session's stages.
+ * sched and terms are device pointers owned by the caller, laid out as for
+ * cm_eval_batch (bf16 bits [S][n_cands][40] and float32 [S][n_cands][8],
+ * 16-byte aligned), and must stay valid and unchanged until the request's
+ * result has been polled or the request canceled. */
+typedef struct {
+    int32_t n_cands;      /* 0 .. max_batch_cands */
+    int32_t k;            /* 1 .. cfg k */
+    const void *sched;
+    const float *terms;
+} cm_request;
+
+/* A completed request.  idx and val are host arrays of capacity `k` (set by
+ * the caller, at least the request's k); the beam is written there as
+ * cm_topk_per_query writes it.  Times are microseconds of a steady clock
+ * since the server was created. */
+typedef struct {
+    int32_t k;            /* in: capacity of idx and val */
+    int32_t n;            /* out: entries written (the request's k) */
+    int32_t *idx;
+    float *val;
+    double t_submit_us;
+    double t_admit_us;
+    double t_done_us;     /* when the worker saw the micro-batch finish */
+} cm_result;
+
+typedef struct {
+    int64_t submitted, completed, canceled;
+    int64_t candidates, rows;    /* of completed requests */
+    int64_t micro_batches;
+    double wall_us;              /* first submission to last completion */
+    double cands_per_s;          /* candidates / wall time */
+    double p50_us, p99_us, max_us;  /* submit-to-done latency of completed requests */
+    int32_t queue_depth;         /* queued now */
+    int32_t in_flight;           /* admitted and unfinished now */
+    int64_t arena_in_use, arena_high_water;
+    double kernel_us;            /* GPU time of the step kernels of completed micro-batches */
+    int64_t kernel_bytes;        /* algorithmic bytes they read and wrote */
+} cm_server_stats;
+
+/* Create a server on the current device for `model`, which must outlive it.
+ * Allocates everything it will use (no allocation while serving) and starts
+ * the worker.  Errors: CM_EINVAL, CM_EUNSUPPORTED (precision), CM_ENOMEM,
+ * CM_EDEVICE. */
+cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_server **out);
+/* Finishes every queued and admitted request, stops the worker and frees
+ * the server.  Results not yet polled are dropped. */
+cm_status cm_server_destroy(cm_server *server);
+
+/* Open a session for a pipeline of n_stages stages with algorithm features
+ * pipe_host (host float32 [n_stages][56]); its hoisted rows are computed on
+ * the device before the call returns.  Errors: CM_EINVAL, CM_E2BIG (too many
+ * stages), CM_EAGAIN (no free session), CM_EDEVICE. */
+cm_status cm_session_open(cm_server *server, const float *pipe_host, int32_t n_stages,
+                          int32_t *session_out);
+/* Close a session: its queued requests are canceled (their poll returns
+ * CM_ECANCELED), an admitted one still completes.  Errors: CM_ENOTFOUND. */
+cm_status cm_session_close(cm_server *server, int32_t session);
+/* The session's latest beam, from device memory: the server's k best
+ * candidates of its most recently completed request ((-1, +inf) before the
+ * first); the first k entries go into host arrays.  Errors: CM_EINVAL (k above the server's), CM_ENOTFOUND,
+ * CM_EAGAIN (a request of the session is in flight), CM_EDEVICE. */
+cm_status cm_session_beam(cm_server *server, int32_t session, int32_t k, int32_t *idx_host,
+                          float *val_host);
+
+/* Queue a request; returns at once with a ticket.  A request takes
+ * n_stages * n_cands * (80 + 32) + n_cands * 4 + k * 8 bytes of the arena
+ * while admitted.  Errors: CM_EINVAL, CM_ENOTFOUND (session), CM_E2BIG (can
+ * never be admitted: larger than the arena or a micro-batch), CM_EAGAIN
+ * (queue full), CM_EDEVICE (the server has failed). */
+cm_status cm_serve_submit(cm_server *server, int32_t session, const cm_request *req,
+                          uint64_t *ticket);
+/* Non-blocking: CM_OK with the result (the ticket is then released),
+ * CM_EAGAIN if not finished, CM_ECANCELED (released), CM_ENOTFOUND,
+ * CM_EINVAL (result capacity too small), CM_EDEVICE (the server failed). */
+cm_status cm_serve_poll(cm_server *server, uint64_t ticket, cm_result *out);
+/* cm_serve_poll that waits up to timeout_ms for the result (CM_EAGAIN after). */
+cm_status cm_serve_wait(cm_server *server, uint64_t ticket, int32_t timeout_ms, cm_result *out);
+
+/* Queue n requests at once (request j for session sessions[j]), as n calls
+ * of cm_serve_submit under one lock; tickets[j] receives each ticket.  All or
+ * nothing: on an error no request is queued.  Errors: as cm_serve_submit. */
+cm_status cm_serve_submit_batch(cm_server *server, int32_t n, const int32_t *sessions,
+                                const cm_request *reqs, uint64_t *tickets);
+/* Wait up to timeout_ms until every one of the n tickets has finished, then
+ * release them, writing results into outs[j] (outs may be NULL to discard
+ * them).  Returns CM_OK when all completed; the first CM_ECANCELED or
+ * CM_EDEVICE otherwise (every finished ticket is still released); CM_EAGAIN
+ * on time-out (nothing released); CM_ENOTFOUND for an unknown ticket;
+ * CM_EINVAL when an outs[j] is too small. */
+cm_status cm_serve_wait_all(cm_server *server, int32_t n, const uint64_t *tickets,
+                            int32_t timeout_ms, cm_result *outs);
+
+cm_status cm_server_get_stats(cm_server *server, cm_server_stats *out);
+/* Clears the counters and latencies (not the queue or arena state). */
+cm_status cm_server_reset_stats(cm_server *server);
 
 /* Thread-local text of the last error on this thread ("" if none). */
 const char *cm_last_error(void);

@@ -19,7 +19,9 @@ __all__ = [
     "CM_FP32", "CM_BF16", "CM_MAX_K", "CmError", "Model", "Workspace", "Batch",
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
     "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
-    "cm_version", "pack_queries",
+    "cm_version", "pack_queries", "Step", "cm_step_create", "cm_step_destroy", "cm_step_run",
+    "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
+    "Server", "cm_server_create",
 ]
 
 PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16}
@@ -163,6 +165,187 @@ def cm_topk_per_query(cost, batch: Batch, k: int, ws: Workspace, idx_out, val_ou
     """The k best candidates per query into idx_out/val_out [n_queries*k]."""
     check(lib().cm_topk_per_query(_ptr(cost), ctypes.byref(batch.c), int(k), ws.handle,
                                   _ptr(idx_out), _ptr(val_out), _stream_handle(stream)))
+
+
+class Step:
+    """Handle of a cm_step (persistent, graph-replayed beam step)."""
+
+    def __init__(self, handle, model):
+        self.handle = handle
+        self.model = model  # the step reads the model's device buffers
+
+    def close(self):
+        if self.handle is not None:
+            check(lib().cm_step_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cm_step_create(model: Model, precision="bf16", max_queries=32, max_stages=4096,
+                   max_cands=1 << 16, max_k=32, slots=2) -> Step:
+    prec = PRECISIONS.get(precision, precision)
+    desc = _lib.cm_step_desc(int(max_queries), int(max_stages), int(max_cands), int(max_k),
+                             int(slots))
+    h = ctypes.c_void_p()
+    check(lib().cm_step_create(model.handle, int(prec), ctypes.byref(desc), ctypes.byref(h)))
+    return Step(h, model)
+
+
+def cm_step_destroy(step: Step):
+    step.close()
+
+
+def cm_step_run(step: Step, batch: Batch, U, k: int, cost_out, idx_out, val_out, stream=None):
+    """Hoist (when U is None) + evaluate + select for every query of the
+    batch, as one persistent launch (replayed as a graph by default)."""
+    check(lib().cm_step_run(step.handle, ctypes.byref(batch.c), _ptr(U), int(k), _ptr(cost_out),
+                            _ptr(idx_out), _ptr(val_out), _stream_handle(stream)))
+
+
+def cm_step_set_config(step: Step, grid=0, group_tiles=1, use_graph=1):
+    cfg = _lib.cm_step_config(int(grid), int(group_tiles), int(use_graph))
+    check(lib().cm_step_set_config(step.handle, ctypes.byref(cfg)))
+
+
+def cm_step_get_config(step: Step) -> dict:
+    cfg = _lib.cm_step_config()
+    check(lib().cm_step_get_config(step.handle, ctypes.byref(cfg)))
+    return dict(grid=cfg.grid, group_tiles=cfg.group_tiles, use_graph=cfg.use_graph)
+
+
+def cm_step_autotune(step: Step, batch: Batch, U, k: int, cost_out, idx_out, val_out,
+                     stream=None, reps=10):
+    """Time the built-in configurations on this batch and keep the fastest.
+    Returns (config dict, median microseconds)."""
+    cfg = _lib.cm_step_config()
+    us = ctypes.c_float()
+    check(lib().cm_step_autotune(step.handle, ctypes.byref(batch.c), _ptr(U), int(k),
+                                 _ptr(cost_out), _ptr(idx_out), _ptr(val_out),
+                                 _stream_handle(stream), int(reps), ctypes.byref(cfg),
+                                 ctypes.byref(us)))
+    return dict(grid=cfg.grid, group_tiles=cfg.group_tiles, use_graph=cfg.use_graph), us.value
+
+
+def cm_step_kernel_time(step: Step) -> float:
+    """Microseconds of the step kernel alone in the step's latest run."""
+    us = ctypes.c_float()
+    check(lib().cm_step_kernel_time(step.handle, ctypes.byref(us)))
+    return us.value
+
+
+class Server:
+    """Handle of a cm_server (continuous batching of beam-step queries)."""
+
+    def __init__(self, handle, model, k):
+        self.handle = handle
+        self.model = model  # the server reads the model's device buffers
+        self.k = k
+
+    def close(self):
+        if self.handle is not None:
+            check(lib().cm_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def session_open(self, pipe) -> int:
+        """Open a session for host algorithm features pipe[S][56] (float32)."""
+        p = np.ascontiguousarray(pipe, dtype=np.float32)
+        sid = ctypes.c_int32()
+        check(lib().cm_session_open(self.handle, p.ctypes.data_as(ctypes.c_void_p),
+                                    int(p.shape[0]), ctypes.byref(sid)))
+        return sid.value
+
+    def session_close(self, sid: int):
+        check(lib().cm_session_close(self.handle, int(sid)))
+
+    def session_beam(self, sid: int, k: int):
+        idx = np.empty(k, np.int32)
+        val = np.empty(k, np.float32)
+        check(lib().cm_session_beam(self.handle, int(sid), int(k),
+                                    idx.ctypes.data_as(ctypes.c_void_p),
+                                    val.ctypes.data_as(ctypes.c_void_p)))
+        return idx, val
+
+    def submit(self, sid: int, n_cands: int, sched, terms, k: int) -> int:
+        """Queue a request over device tensors sched (bf16 [S][N][40]) and
+        terms (float32 [S][N][8]); the tensors must outlive the request."""
+        r = _lib.cm_request(int(n_cands), int(k), _ptr(sched), _ptr(terms))
+        t = ctypes.c_uint64()
+        check(lib().cm_serve_submit(self.handle, int(sid), ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def _result(self, k):
+        idx = np.empty(k, np.int32)
+        val = np.empty(k, np.float32)
+        res = _lib.cm_result(k, 0, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 0.0, 0.0, 0.0)
+        return res, idx, val
+
+    def poll(self, ticket: int):
+        """None while the request is not finished, else (idx, val, times)."""
+        res, idx, val = self._result(self.k)
+        st = lib().cm_serve_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if st == _lib.CM_EAGAIN:
+            return None
+        check(st)
+        return idx[:res.n], val[:res.n], (res.t_submit_us, res.t_admit_us, res.t_done_us)
+
+    def wait(self, ticket: int, timeout_ms: int = 10000):
+        res, idx, val = self._result(self.k)
+        check(lib().cm_serve_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_ms),
+                                  ctypes.byref(res)))
+        return idx[:res.n], val[:res.n], (res.t_submit_us, res.t_admit_us, res.t_done_us)
+
+    def submit_batch(self, sessions, n_cands, sched_ptrs, terms_ptrs, k):
+        """Queue len(sessions) requests in one call.  sched_ptrs/terms_ptrs
+        are device addresses (ints) of each request's inputs.  Returns the
+        tickets as a uint64 array."""
+        n = len(sessions)
+        sess = np.ascontiguousarray(sessions, dtype=np.int32)
+        reqs = (_lib.cm_request * max(n, 1))()
+        for j in range(n):
+            reqs[j] = _lib.cm_request(int(n_cands[j]), int(k), ctypes.c_void_p(int(sched_ptrs[j])),
+                                      ctypes.c_void_p(int(terms_ptrs[j])))
+        tickets = np.zeros(max(n, 1), np.uint64)
+        check(lib().cm_serve_submit_batch(self.handle, n, sess.ctypes.data_as(ctypes.c_void_p),
+                                          reqs, tickets.ctypes.data_as(ctypes.c_void_p)))
+        return tickets[:n]
+
+    def wait_all(self, tickets, timeout_ms: int = 60000):
+        """Wait for every ticket and release them (results discarded)."""
+        t = np.ascontiguousarray(tickets, dtype=np.uint64)
+        check(lib().cm_serve_wait_all(self.handle, len(t), t.ctypes.data_as(ctypes.c_void_p),
+                                      int(timeout_ms), None))
+
+    def stats(self) -> dict:
+        s = _lib.cm_server_stats()
+        check(lib().cm_server_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _lib.cm_server_stats._fields_}
+
+    def reset_stats(self):
+        check(lib().cm_server_reset_stats(self.handle))
+
+
+def cm_server_create(model: Model, k=32, arena_bytes=8 << 30, max_slots=2, max_pending=4096,
+                     max_sessions=256, max_stages=128, max_batch_queries=64,
+                     max_batch_cands=1 << 17, precision="bf16") -> Server:
+    prec = PRECISIONS.get(precision, precision)
+    cfg = _lib.cm_server_cfg(int(prec), int(k), int(arena_bytes), int(max_slots),
+                             int(max_pending), int(max_sessions), int(max_stages),
+                             int(max_batch_queries), int(max_batch_cands))
+    h = ctypes.c_void_p()
+    check(lib().cm_server_create(model.handle, ctypes.byref(cfg), ctypes.byref(h)))
+    return Server(h, model, int(k))
 
 
 def pack_queries(queries, precision, device="cuda"):

@@ -20,11 +20,18 @@ CM_FP32, CM_BF16 = 0, 1
 CM_MAX_K = 256
 CM_N_PARAMS = 4184
 CM_STAGE_CHUNK = 16
+CM_STEP_MAX_QUERIES = 256
 
 # Every function the header declares, for the export check.
 EXPORTS = (
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
     "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
+    "cm_step_create", "cm_step_destroy", "cm_step_run", "cm_step_set_config",
+    "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
+    "cm_server_create", "cm_server_destroy", "cm_session_open", "cm_session_close",
+    "cm_session_beam", "cm_serve_submit", "cm_serve_poll", "cm_serve_wait",
+    "cm_serve_submit_batch", "cm_serve_wait_all",
+    "cm_server_get_stats", "cm_server_reset_stats",
     "cm_last_error", "cm_version",
 )
 
@@ -53,6 +60,49 @@ class cm_batch(ctypes.Structure):
                 ("terms", ctypes.c_void_p)]
 
 
+class cm_step_desc(ctypes.Structure):
+    _fields_ = [("max_queries", ctypes.c_int32), ("max_stages", ctypes.c_int64),
+                ("max_cands", ctypes.c_int64), ("max_k", ctypes.c_int32),
+                ("slots", ctypes.c_int32)]
+
+
+class cm_step_config(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("group_tiles", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class cm_server_cfg(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("max_sessions", ctypes.c_int32),
+                ("max_stages", ctypes.c_int32), ("max_batch_queries", ctypes.c_int32),
+                ("max_batch_cands", ctypes.c_int64)]
+
+
+class cm_request(ctypes.Structure):
+    _fields_ = [("n_cands", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("sched", ctypes.c_void_p), ("terms", ctypes.c_void_p)]
+
+
+class cm_result(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("idx", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_float)),
+                ("t_submit_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double)]
+
+
+class cm_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("canceled", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("rows", ctypes.c_int64), ("micro_batches", ctypes.c_int64),
+                ("wall_us", ctypes.c_double), ("cands_per_s", ctypes.c_double),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("queue_depth", ctypes.c_int32),
+                ("in_flight", ctypes.c_int32), ("arena_in_use", ctypes.c_int64),
+                ("arena_high_water", ctypes.c_int64), ("kernel_us", ctypes.c_double),
+                ("kernel_bytes", ctypes.c_int64)]
+
+
 class CmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -78,9 +128,37 @@ def lib():
         L.cm_hoist_stages.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp]
         L.cm_eval_hoisted.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp, vp, vp]
         L.cm_topk_per_query.argtypes = [vp, ctypes.POINTER(cm_batch), i32, vp, vp, vp, vp]
+        L.cm_step_create.argtypes = [vp, i32, ctypes.POINTER(cm_step_desc), ctypes.POINTER(vp)]
+        L.cm_step_destroy.argtypes = [vp]
+        L.cm_step_run.argtypes = [vp, ctypes.POINTER(cm_batch), vp, i32, vp, vp, vp, vp]
+        L.cm_step_set_config.argtypes = [vp, ctypes.POINTER(cm_step_config)]
+        L.cm_step_get_config.argtypes = [vp, ctypes.POINTER(cm_step_config)]
+        L.cm_step_autotune.argtypes = [vp, ctypes.POINTER(cm_batch), vp, i32, vp, vp, vp, vp,
+                                       i32, ctypes.POINTER(cm_step_config),
+                                       ctypes.POINTER(ctypes.c_float)]
+        L.cm_step_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+        L.cm_server_create.argtypes = [vp, ctypes.POINTER(cm_server_cfg), ctypes.POINTER(vp)]
+        L.cm_server_destroy.argtypes = [vp]
+        L.cm_session_open.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+        L.cm_session_close.argtypes = [vp, i32]
+        L.cm_session_beam.argtypes = [vp, i32, i32, vp, vp]
+        L.cm_serve_submit.argtypes = [vp, i32, ctypes.POINTER(cm_request),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+        L.cm_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(cm_result)]
+        L.cm_serve_wait.argtypes = [vp, ctypes.c_uint64, i32, ctypes.POINTER(cm_result)]
+        L.cm_serve_submit_batch.argtypes = [vp, i32, vp, ctypes.POINTER(cm_request), vp]
+        L.cm_serve_wait_all.argtypes = [vp, i32, vp, i32, ctypes.POINTER(cm_result)]
+        L.cm_server_get_stats.argtypes = [vp, ctypes.POINTER(cm_server_stats)]
+        L.cm_server_reset_stats.argtypes = [vp]
         for f in ("cm_model_create", "cm_model_destroy", "cm_workspace_create",
                   "cm_workspace_destroy", "cm_eval_batch", "cm_hoist_stages",
-                  "cm_eval_hoisted", "cm_topk_per_query"):
+                  "cm_eval_hoisted", "cm_topk_per_query", "cm_step_create",
+                  "cm_step_destroy", "cm_step_run", "cm_step_set_config",
+                  "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
+                  "cm_server_create", "cm_server_destroy", "cm_session_open",
+                  "cm_session_close", "cm_session_beam", "cm_serve_submit", "cm_serve_poll",
+                  "cm_serve_wait", "cm_server_get_stats", "cm_server_reset_stats",
+                  "cm_serve_submit_batch", "cm_serve_wait_all"):
             getattr(L, f).restype = i32
         L.cm_last_error.restype = ctypes.c_char_p
         L.cm_last_error.argtypes = []

@@ -11,16 +11,15 @@
 
 #include "cm_internal.h"
 
-struct cm_model {
-    cm::Model m;
-};
 struct cm_workspace {
     cm::Workspace w;
 };
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace cm {
 
 cm_status fail(cm_status st, const char *fmt, ...)
 {
@@ -33,12 +32,11 @@ cm_status fail(cm_status st, const char *fmt, ...)
     return st;
 }
 
-#define CM_HIP(expr)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(CM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-    } while (0)
+}  // namespace cm
+
+namespace {
+
+using cm::fail;
 
 uint16_t f32_to_bf16(float f)  // round to nearest even
 {

@@ -101,6 +101,73 @@ struct TopkLaunch {
     TopkQ q[QMAX];
 };
 
+// ------------------------------------------------------------------ step
+// Device-resident descriptors of one persistent step (hoist + evaluate +
+// select).  The host writes them into pinned memory and one copy moves them
+// to the device ahead of the kernels, so the launch configuration never
+// depends on the batch and the whole step can be replayed as a graph.
+constexpr int STEP_MAX_QUERIES = CM_STEP_MAX_QUERIES;
+
+struct StepQ {
+    const uint16_t *x;  // schedule features [S][N][40], bf16
+    const float *t;     // cost terms [S][N][8]
+    float *u;           // hoisted rows [S][32] (written by the hoist when it runs)
+    const float *pipe;  // algorithm features [S][56] (hoist only)
+    float *cost;        // [N]
+    int32_t *idx;       // beam [k]
+    float *val;         // beam costs [k]
+    int32_t *sidx;      // second copy of the beam (a session's), or null
+    float *sval;
+    int32_t S, N;
+    int32_t task0;      // first task of this query
+    int32_t ntasks;     // >= 1 (a query with no candidates still writes its padding)
+    int32_t parts;      // stage parts P
+    int32_t row0;       // first hoist row of this query
+    int32_t tile0;      // first selection tile (global numbering)
+    int32_t ntiles;     // selection tiles of TOPK_TILE candidates, >= 1
+};
+
+struct StepHead {
+    int32_t nq;        // queries
+    int32_t ntasks;    // tasks over all queries
+    int32_t nrows;     // hoist rows over all queries
+    int32_t k;         // beam width
+    int32_t gpt;       // row-tile groups per task (1, 2 or 4)
+    int32_t pad[3];
+};
+
+// Control words of a step, zero between steps (the step kernel leaves them
+// zero when it ends): task queue head, exit count, per-query and per-tile
+// arrival counts.
+constexpr int CTL_NEXT = 0;
+constexpr int CTL_DONE = 32;
+constexpr int CTL_QCNT = 64;
+constexpr int CTL_TCNT = CTL_QCNT + STEP_MAX_QUERIES;
+
+// One query of a step, as absolute device pointers (host side).
+struct StepReq {
+    const uint16_t *x;
+    const float *t;
+    float *u;
+    const float *pipe;  // needed only when the step hoists
+    float *cost;
+    int32_t *idx;
+    float *val;
+    int32_t *sidx;      // optional second beam destination
+    float *sval;
+    int32_t S, N;
+};
+
+// Queue one step over `n` queries on `st` (validated by the caller against
+// the step's capacities; n <= max_queries, sum N <= max_cands, sum S <=
+// max_stages when hoisting).
+cm_status step_launch(cm_step *S, const StepReq *r, int n, int k, bool hoist, hipStream_t st);
+// Capacities of a step.
+const cm_step_desc &step_caps(const cm_step *S);
+// Kernel-only GPU time (microseconds) of the step's most recent launch,
+// waiting for it if it is still running.
+cm_status step_kernel_us(cm_step *S, float *us);
+
 // Kernel launchers (one per translation unit).
 hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, const float *pipe,
                         float *U, hipStream_t st);
@@ -110,5 +177,46 @@ hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t 
                             const float *terms, const float *U, float *cost, hipStream_t st);
 hipError_t launch_topk(const TopkLaunch &L, const float *cost, uint64_t *tpart, int32_t *tcnt,
                        int32_t *idx_out, float *val_out, hipStream_t st);
+hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m, int grid,
+                             hipStream_t st);
+hipError_t launch_step_bf16(const StepHead *h, const StepQ *qs, uint32_t *ctl, uint64_t *tpart,
+                            const Model &m, int grid, hipStream_t st);
+
+// Device side: data one workgroup hands to another inside a launch (costs
+// read by the selecting workgroup, per-tile beam lists) is stored and loaded
+// with agent-scope atomic accesses, which bypass the per-XCD L2's
+// non-coherent copies, and the producer waits for its stores to complete
+// before its arrival count.  This replaces device-wide fences, which write
+// back and invalidate the whole L2.
+// (Pointers are taken as global memory, so the accesses are global, not
+// flat, instructions and the store wait below covers them.)
+template <class T>
+__device__ inline void store_shared(T *p, T v)
+{
+    __hip_atomic_store((__attribute__((address_space(1))) T *)p, v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline T load_shared(const T *p)
+{
+    return __hip_atomic_load((__attribute__((address_space(1))) T *)const_cast<T *>(p),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wave's stores have completed.
+__device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Host side: record a thread-local error message and return `st`.
+cm_status fail(cm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define CM_HIP(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::cm::fail(CM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
 
 }  // namespace cm
+
+struct cm_model {
+    cm::Model m;
+};

@@ -1,0 +1,347 @@
+// eval_bf16.h -- device code of the bf16 matrix-core evaluator of the cost
+// model (Sec. 5.2), shared by the per-call kernel and the persistent step
+// kernel so that both give bit-identical results.
+//
+// Work unit = one wavefront x (32 candidates of one query) x (one part of the
+// query's stages; stage_parts() splits them into 1, 2, 4 or 8 contiguous
+// parts by stage count alone).  A group of 8 waves holds every part of its
+// row tiles.  Per stage the wave
+//   1. loads the 32 candidates' bf16 schedule features (stage-major rows of
+//      80 bytes; each row is split over two lanes, 40 bytes each) and their
+//      float32 cost terms, one stage ahead of the arithmetic;
+//   2. takes log2(1 + x) in float32 (ln 2 is folded into the weights, so the
+//      layer sees log1p(x)) and splits it into high and low bf16 parts;
+//   3. runs the first layer as D[hidden][cand] = Wf . X^T on the 32x32x16 bf16
+//      matrix core: Wf = W_1[:, 24:] W_s is the schedule embedding folded into
+//      the first layer (no activation sits between them), the accumulator
+//      starts from the hoisted per-stage vector U[s] (algorithm embedding,
+//      biases), and each product is hi*hi + lo*hi + hi*lo;
+//   4. applies the ReLU, splits the hidden activations the same way and runs
+//      the coefficient layer (8 outputs padded to 32) on the matrix core; the
+//      hidden order is permuted in the packed weights so that the first
+//      layer's output registers are already the second layer's operands;
+//   5. applies the ReLU to the 8 coefficients, dots them with the 8 cost
+//      terms (two lanes hold four each and exchange halves) and adds the
+//      stage prediction to a Kahan-compensated float32 sum (App. B).
+// Each part's (sum, compensation) pair goes through LDS and the first wave of
+// the tile combines the parts in ascending order, so the result of a
+// candidate depends only on its query, never on the batch, the launch shape
+// or timing, and no device-wide synchronisation is needed.
+#pragma once
+
+#include "cm_internal.h"
+
+namespace cm {
+namespace bf16eval {
+
+
+constexpr int USTAGE = 16;  // hoisted rows staged in LDS per refill
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline uint32_t pack_bf16x2(float a, float b)
+{
+    bf16x2 v = {(__bf16)a, (__bf16)b};  // round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// A packed pair of bf16 constants kept in a register.  The dot instruction
+// below must not see them as inline constants: an inline constant in a
+// packed-bf16 operand does not select the same halves as the compiler
+// assumes, so the value is hidden from constant folding.
+__device__ inline bf16x2 pair_reg(uint32_t bits)
+{
+    uint32_t v;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(v) : "i"(bits));
+    return __builtin_bit_cast(bf16x2, v);
+}
+
+// c + (one bf16 of w) * (the matching bf16 of m): the product of two bf16
+// values is exact in float32 and the sum is rounded once.
+__device__ inline float dot(uint32_t w, bf16x2 m, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), m, c, false);
+}
+
+struct Pairs {
+    bf16x2 one_lo, one_hi, neg_lo, neg_hi;  // (1,0) (0,1) (-1,0) (0,-1)
+};
+
+__device__ inline Pairs make_pairs()
+{
+    return Pairs{pair_reg(0x00003f80u), pair_reg(0x3f800000u), pair_reg(0x0000bf80u),
+                 pair_reg(0xbf800000u)};
+}
+
+// Two float values -> (high bf16 pair, low bf16 pair) with a ~= hi + lo:
+// hi rounds to nearest, lo = a - hi is exact in float32 before its rounding.
+__device__ inline void split2(float a, float b, uint32_t &hi, uint32_t &lo, const Pairs &k)
+{
+    hi = pack_bf16x2(a, b);
+    lo = pack_bf16x2(dot(hi, k.neg_lo, a), dot(hi, k.neg_hi, b));
+}
+
+// 8 raw bf16 features -> high/low bf16 operands of log2(1 + x).
+__device__ inline void log_split(uint4 raw, bf16x8 &hi, bf16x8 &lo, const Pairs &k)
+{
+    uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const float y0 = __builtin_amdgcn_logf(dot(w[d], k.one_lo, 1.0f));
+        const float y1 = __builtin_amdgcn_logf(dot(w[d], k.one_hi, 1.0f));
+        split2(y0, y1, h[d], l[d], k);
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+// 4 raw bf16 features (plus 4 zero slots) -> high/low operands.
+__device__ inline void log_split4(uint2 raw, bf16x8 &hi, bf16x8 &lo, const Pairs &k)
+{
+    uint32_t w[2] = {raw.x, raw.y};
+    uint32_t h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const float y0 = __builtin_amdgcn_logf(dot(w[d], k.one_lo, 1.0f));
+        const float y1 = __builtin_amdgcn_logf(dot(w[d], k.one_hi, 1.0f));
+        split2(y0, y1, h[d], l[d], k);
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+// ReLU that lets a NaN through, like the oracle
+__device__ inline float relu(float x) { return x < 0.f ? 0.f : x; }
+
+__device__ inline void kahan_add(float &s, float &c, float v)
+{
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+__device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Sum of a value held by lane l and lane l ^ 32, identical in both lanes.
+__device__ inline float add_halves(float v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// One stage's operands for one lane: features 16*st + 8*hf .. +8 for st = 0, 1,
+// features 32 + 4*hf .. +4, and cost terms 4*hf .. +4.
+struct StageIn {
+    uint4 x0, x1;
+    uint2 x2;
+    float4 t;
+};
+
+// xs, ts: the stage's rows (uniform); xo, x2o, to: this lane's byte offsets
+__device__ inline void load_stage(StageIn &in, const char *xs, const char *ts, uint32_t xo,
+                                  uint32_t x2o, uint32_t to)
+{
+    in.x0 = *reinterpret_cast<const uint4 *>(xs + xo);
+    in.x1 = *reinterpret_cast<const uint4 *>(xs + xo + 32);
+    in.x2 = *reinterpret_cast<const uint2 *>(xs + x2o);
+    in.t = *reinterpret_cast<const float4 *>(ts + to);
+}
+
+struct Weights {
+    bf16x8 A1h[3], A1l[3], A2h[2], A2l[2];
+    float b2v[4];
+};
+
+// Refill this wave's LDS slice with the hoisted rows of stages s .. s+n-1.
+// Only this wave reads its slice and its LDS operations complete in order.
+__device__ inline void refill_u(float4 *ur, const float4 *ug, int s, int n, int lane)
+{
+    const int nv = n * (H / 4);
+    for (int v = lane; v < nv; v += 64) ur[v] = ug[(int64_t)s * (H / 4) + v];
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One stage of 32 candidates: both dense layers on the matrix cores, the
+// coefficient dot product with the cost terms, and the compensated sum.
+__device__ __forceinline__ void stage_math(const StageIn &in, const float4 *us, int hf,
+                                           const Weights &w, const Pairs &kp, float &sum,
+                                           float &comp)
+{
+    // first layer: accumulator starts from U[s]; register g*4+j holds
+    // hidden unit g*8 + hf*4 + j
+    f32x16 acc;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 u4 = us[g * 2 + hf];
+        acc[g * 4 + 0] = u4.x;
+        acc[g * 4 + 1] = u4.y;
+        acc[g * 4 + 2] = u4.z;
+        acc[g * 4 + 3] = u4.w;
+    }
+    bf16x8 bh, bl;
+    log_split(in.x0, bh, bl, kp);
+    acc = mfma(w.A1h[0], bh, acc);
+    acc = mfma(w.A1l[0], bh, acc);
+    acc = mfma(w.A1h[0], bl, acc);
+    log_split(in.x1, bh, bl, kp);
+    acc = mfma(w.A1h[1], bh, acc);
+    acc = mfma(w.A1l[1], bh, acc);
+    acc = mfma(w.A1h[1], bl, acc);
+    log_split4(in.x2, bh, bl, kp);
+    acc = mfma(w.A1h[2], bh, acc);
+    acc = mfma(w.A1l[2], bh, acc);
+    acc = mfma(w.A1h[2], bl, acc);
+
+    // coefficient layer (output registers 0..3 are the 8 real outputs); its
+    // bias is added after the products
+    f32x16 acc2;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        uint32_t hh[4], hl[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            split2(relu(acc[t * 8 + 2 * d]), relu(acc[t * 8 + 2 * d + 1]), hh[d], hl[d], kp);
+        const bf16x8 Hh = __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
+        const bf16x8 Hl = __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
+        acc2 = mfma(w.A2h[t], Hh, acc2);
+        acc2 = mfma(w.A2l[t], Hh, acc2);
+        acc2 = mfma(w.A2h[t], Hl, acc2);
+    }
+    // lanes hf=0 hold coefficients 0..3 of their candidate, hf=1 hold 4..7
+    float v = relu(acc2[0] + w.b2v[0]) * in.t.x;
+    v = fmaf(relu(acc2[1] + w.b2v[1]), in.t.y, v);
+    v = fmaf(relu(acc2[2] + w.b2v[2]), in.t.z, v);
+    v = fmaf(relu(acc2[3] + w.b2v[3]), in.t.w, v);
+    kahan_add(sum, comp, add_halves(v));
+}
+
+// Load this lane's packed operands of both layers (held for the whole wave).
+__device__ inline Weights load_weights(const Bf16Pack *__restrict__ pk, int lane)
+{
+    Weights w;
+    const int hf = lane >> 5;
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+        w.A1h[st] = __builtin_bit_cast(bf16x8, pk->a1[0][st][lane]);
+        w.A1l[st] = __builtin_bit_cast(bf16x8, pk->a1[1][st][lane]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        w.A2h[t] = __builtin_bit_cast(bf16x8, pk->a2[0][t][lane]);
+        w.A2l[t] = __builtin_bit_cast(bf16x8, pk->a2[1][t][lane]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w.b2v[r] = pk->b2[hf * 4 + r];
+    return w;
+}
+
+// One query as the evaluator reads it.
+struct QueryView {
+    const uint16_t *x;  // schedule features [S][N][40], bf16
+    const float *t;     // cost terms [S][N][8]
+    const float *u;     // hoisted rows [S][32]
+    float *cost;        // [N]
+    int S, N, P;
+};
+
+// LDS of one group of EVAL_WAVES waves.
+struct GroupShared {
+    float2 part[EVAL_WAVES][TILE_ROWS];
+    float4 u[EVAL_WAVES][USTAGE * H / 4];
+};
+
+// Evaluate row-tile group `group` of a query: EVAL_WAVES / P tiles of 32
+// candidates, every wave one (tile, stage part).  Every thread of the
+// EVAL_WAVES-wave workgroup must call this with the same arguments (it
+// synchronises the workgroup when P > 1).  kShared: the costs are read by
+// another workgroup of the same launch (coherent stores).
+template <bool kShared>
+__device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wave, int lane,
+                                           const Weights &w, const Pairs &kp, GroupShared &sh)
+{
+    const int P = Q.P;
+    const int tile = group * (EVAL_WAVES / P) + wave / P;
+    const int part = wave % P;
+    const int n = lane & 31;
+    const int hf = lane >> 5;
+    const int i = tile * TILE_ROWS + n;
+    const bool valid = i < Q.N;
+    // rows past the end of the query read the last row instead: every load
+    // stays in bounds and the results of those rows are never stored
+    const int ic = valid ? i : Q.N - 1;
+    // stages [s0, s1) of this part; a tile past the query's end does no work
+    const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
+    const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
+
+    // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart
+    const int64_t xstep = (int64_t)Q.N * FS * 2;
+    const int64_t tstep = (int64_t)Q.N * C * 4;
+    const char *xs = reinterpret_cast<const char *>(Q.x) + s0 * xstep;
+    const char *ts = reinterpret_cast<const char *>(Q.t) + s0 * tstep;
+    const uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
+    const uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
+    const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
+    const float4 *ug = reinterpret_cast<const float4 *>(Q.u);
+    // this wave's slice of LDS holds the hoisted rows of up to USTAGE stages
+    float4 *ur = sh.u[wave];
+
+    float sum = 0.f, comp = 0.f;
+    if (s0 < s1) {
+        // two register buffers alternate so that a stage's loads stay in
+        // flight during the previous stage's arithmetic without copies
+        StageIn A, B;
+        load_stage(A, xs, ts, xo, x2o, to);
+        for (int s = s0; s < s1; s += 2) {
+            if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
+            if (s + 1 < s1) {
+                xs += xstep;
+                ts += tstep;
+            }
+            load_stage(B, xs, ts, xo, x2o, to);
+            // keep the loads here, ahead of their use (the feature pointers
+            // are not restrict-qualified, so the compiler cannot move them
+            // across this)
+            asm volatile("" ::: "memory");
+            stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            if (s + 1 >= s1) break;
+
+            if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
+            if (s + 2 < s1) {
+                xs += xstep;
+                ts += tstep;
+            }
+            load_stage(A, xs, ts, xo, x2o, to);
+            asm volatile("" ::: "memory");
+            stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+        }
+    }
+
+    // combine the parts of each tile in ascending order
+    if (P > 1) {
+        if (hf == 0) sh.part[wave][n] = make_float2(sum, comp);
+        __syncthreads();
+    }
+    if (part == 0 && hf == 0 && valid) {
+        float S = 0.f, Cc = 0.f;
+        for (int p = 0; p < P; ++p) {
+            const float2 pc = P > 1 ? sh.part[wave + p][n] : make_float2(sum, comp);
+            kahan_add(S, Cc, pc.x);
+            kahan_add(S, Cc, -pc.y);
+        }
+        if (kShared) store_shared(Q.cost + i, S - Cc);
+        else Q.cost[i] = S - Cc;
+    }
+}
+
+}  // namespace bf16eval
+}  // namespace cm

@@ -28,16 +28,11 @@ __device__ inline int find_query(const EvalLaunch &L, int t, bool by_stage)
     return q;
 }
 
-__global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restrict__ params,
-                                              const float *__restrict__ beta, int fold,
-                                              const float *__restrict__ pipe,
-                                              float *__restrict__ U)
+// One stage row of the hoist by a 64-thread workgroup: p = the stage's 56
+// algorithm features, u = its 32 output floats.
+__device__ inline void hoist_row(const float *__restrict__ params, const float *__restrict__ beta,
+                                 int fold, const float *p, float *u, float *lp, float *ep)
 {
-    __shared__ float lp[FP];
-    __shared__ float ep[E];
-    const int q = find_query(L, blockIdx.x, true);
-    const int s = blockIdx.x - L.q[q].hrow0;
-    const float *p = pipe + L.q[q].pipe_off + (int64_t)s * FP;
     const int t = threadIdx.x;
     if (t < FP) lp[t] = log1pf(p[t]);
     __syncthreads();
@@ -53,7 +48,48 @@ __global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restr
         float a = params[OFF_B1 + t];
         for (int e = 0; e < E; ++e) a = fmaf(w[e], ep[e], a);
         if (fold) a += beta[t];
-        U[L.q[q].u_off + (int64_t)s * H + t] = a;
+        u[t] = a;
+    }
+    __syncthreads();  // lp and ep are reused by the next row
+}
+
+__global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restrict__ params,
+                                              const float *__restrict__ beta, int fold,
+                                              const float *__restrict__ pipe,
+                                              float *__restrict__ U)
+{
+    __shared__ float lp[FP];
+    __shared__ float ep[E];
+    const int q = find_query(L, blockIdx.x, true);
+    const int s = blockIdx.x - L.q[q].hrow0;
+    hoist_row(params, beta, fold, pipe + L.q[q].pipe_off + (int64_t)s * FP,
+              U + L.q[q].u_off + (int64_t)s * H, lp, ep);
+}
+
+// Hoist of a step: the rows of every query, grid-stride, from the device
+// descriptors (the bf16 evaluator's form, with W_1[:, 24:] b_s folded in).
+__global__ __launch_bounds__(64) void k_hoist_step(const StepHead *__restrict__ h,
+                                                   const StepQ *__restrict__ qs,
+                                                   const float *__restrict__ params,
+                                                   const float *__restrict__ beta)
+{
+    __shared__ int32_t row0[STEP_MAX_QUERIES];
+    __shared__ float lp[FP];
+    __shared__ float ep[E];
+    const int nq = h->nq, nrows = h->nrows;
+    for (int j = threadIdx.x; j < nq; j += 64) row0[j] = qs[j].row0;
+    __syncthreads();
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        // the last query whose first row is <= r
+        int lo = 0, hi = nq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (row0[mid] <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        const StepQ &D = qs[lo];
+        const int s = r - row0[lo];
+        hoist_row(params, beta, 1, D.pipe + (int64_t)s * FP, D.u + (int64_t)s * H, lp, ep);
     }
 }
 
@@ -131,6 +167,13 @@ hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, const fl
     if (L.nstages == 0) return hipSuccess;
     hipLaunchKernelGGL(k_hoist, dim3(L.nstages), dim3(64), 0, st, L, m.d_params, m.d_beta,
                        fold ? 1 : 0, pipe, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m, int grid,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hoist_step, dim3(grid), dim3(64), 0, st, h, qs, m.d_params, m.d_beta);
     return hipGetLastError();
 }
 

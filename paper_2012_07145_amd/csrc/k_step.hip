@@ -1,0 +1,156 @@
+// k_step.hip -- the persistent step kernel: bf16 evaluation of many ragged
+// queries (Sec. 5.2) and each query's beam selection (Sec. 4, Sec. 4.4) in
+// one launch whose shape never depends on the batch.
+//
+// A fixed grid of workgroups (8 waves each) takes tasks from a device-wide
+// queue (one atomic add per task, fetched one task ahead).  A task is `gpt`
+// consecutive row-tile groups of one query, evaluated exactly as the
+// per-call kernel does (eval_bf16.h), so the costs are bit-identical to it.
+// Tasks never straddle a selection tile of TOPK_TILE candidates; the
+// workgroup whose task completes a tile (an arrival count per tile) selects
+// that tile's k best, and for a query of several tiles the last tile to
+// finish merges their lists.  A query's selection therefore runs while other queries are
+// still being evaluated.  All control words are left at zero when the
+// kernel ends, so the next launch needs no clearing.
+#include "eval_bf16.h"
+#include "topk_dev.h"
+
+namespace cm {
+namespace {
+
+using namespace bf16eval;
+using namespace topk;
+
+constexpr int NT = EVAL_WAVES * 64;
+
+// Selection of tile `tile` of query q after the last of its tasks has
+// arrived, and for a query of several tiles, the merge by the last tile.
+__device__ void select_tile(const StepQ &D, int q, int tile, int k, uint32_t *qcnt,
+                            uint64_t *tpart, TopkShared<NT> &tsh, int &s_query_last)
+{
+    const int tid = threadIdx.x;
+    uint64_t key[TopkShared<NT>::PER];
+    int nvalid;
+    tile_keys<NT, true>(D.cost, D.N, tile, key, nvalid);
+    int nbest = tile_select<NT>(key, nvalid, k, tsh);
+    bool write = true;
+    if (D.ntiles > 1) {
+        publish_list<NT>(tsh, nbest, k, tpart + (int64_t)(D.tile0 + tile) * k);
+        __syncthreads();
+        if (tid == 0) s_query_last = atomicAdd(&qcnt[q], 1u) == (uint32_t)(D.ntiles - 1);
+        __syncthreads();
+        write = s_query_last;
+        if (write) {
+            if (tid == 0) atomicExch(&qcnt[q], 0u);
+            nbest = merge_lists<NT>(tpart + (int64_t)D.tile0 * k, D.ntiles, D.N, k, tsh);
+        }
+    }
+    if (write) {
+        write_beam<NT, true>(tsh, nbest, k, D.cost, D.idx, D.val);
+        if (D.sidx) write_beam<NT, true>(tsh, nbest, k, D.cost, D.sidx, D.sval);
+    }
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_step_bf16(
+    const StepHead *__restrict__ h, const StepQ *__restrict__ qs, uint32_t *ctl,
+    uint64_t *tpart, const Bf16Pack *__restrict__ pk)
+{
+    __shared__ GroupShared gsh;
+    __shared__ TopkShared<NT> tsh;
+    __shared__ int32_t task0[STEP_MAX_QUERIES];
+    __shared__ int s_next, s_tail, s_query_last;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nq = h->nq, ntasks = h->ntasks, k = h->k, gpt = h->gpt;
+    uint32_t *qcnt = ctl + CTL_QCNT;
+    uint32_t *tcnt = ctl + CTL_TCNT;
+
+    for (int j = tid; j < nq; j += NT) task0[j] = qs[j].task0;
+    if (tid == 0) s_next = (int)atomicAdd(&ctl[CTL_NEXT], 1u);
+    const Pairs kp = make_pairs();
+    __syncthreads();
+    int t = s_next;
+    // The arrival of a task at its selection tile is counted when the task
+    // ends, and its result is looked at only when the next task ends (or
+    // when the workgroup leaves), so no wave waits for the count: the tile
+    // of an earlier task (q_prev, tile_prev) is selected one task later.
+    uint32_t arrived = 0;    // thread 0: the count before this workgroup's arrival
+    uint32_t need = 0;       // thread 0: arrivals that complete that tile
+    int q_prev = -1, tile_prev = 0;
+    while (t < ntasks) {
+        __syncthreads();  // every thread has read s_next
+        if (tid == 0) s_next = (int)atomicAdd(&ctl[CTL_NEXT], 1u);  // next task, fetched early
+        // the query of task t: the last q with task0[q] <= t
+        int lo = 0, hi = nq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (task0[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int q = __builtin_amdgcn_readfirstlane(lo);
+        const StepQ &D = qs[q];
+        QueryView Q;
+        Q.x = D.x;
+        Q.t = D.t;
+        Q.u = D.u;
+        Q.cost = D.cost;
+        Q.S = D.S;
+        Q.N = D.N;
+        Q.P = D.parts;
+        const int tq = t - D.task0;  // task within the query
+        const int group_rows = TILE_ROWS * (EVAL_WAVES / Q.P);
+        {
+            const Weights w = load_weights(pk, lane);
+            for (int g = 0; g < gpt; ++g) {
+                const int group = tq * gpt + g;
+                if (group * group_rows >= Q.N) break;  // uniform
+                eval_group<true>(Q, group, wave, lane, w, kp, gsh);
+                __syncthreads();  // the group's LDS is reused by the next group
+            }
+        }
+        // this task's costs (coherent stores) are complete before it arrives
+        const int tpt = TOPK_TILE / (group_rows * gpt);  // tasks per tile
+        const int tile = tq / tpt;
+        wait_stores();
+        __syncthreads();
+        if (tid == 0) {
+            s_tail = q_prev >= 0 && arrived == need - 1;  // the previous task's arrival
+            need = (uint32_t)min(tpt, D.ntasks - tile * tpt);
+            arrived = atomicAdd(&tcnt[D.tile0 + tile], 1u);  // looked at one task later
+        }
+        __syncthreads();
+        if (s_tail) {
+            if (tid == 0) atomicExch(&tcnt[qs[q_prev].tile0 + tile_prev], 0u);
+            select_tile(qs[q_prev], q_prev, tile_prev, k, qcnt, tpart, tsh, s_query_last);
+        }
+        q_prev = q;
+        tile_prev = tile;
+        __syncthreads();  // s_next is written; the selection's LDS is free
+        t = s_next;
+    }
+    // the last arrival of this workgroup
+    if (tid == 0) s_tail = q_prev >= 0 && arrived == need - 1;
+    __syncthreads();
+    if (s_tail) {
+        if (tid == 0) atomicExch(&tcnt[qs[q_prev].tile0 + tile_prev], 0u);
+        select_tile(qs[q_prev], q_prev, tile_prev, k, qcnt, tpart, tsh, s_query_last);
+    }
+    // the last workgroup to leave resets the queue for the next launch: every
+    // other workgroup has made its final queue fetch before counting itself
+    if (tid == 0 && atomicAdd(&ctl[CTL_DONE], 1u) == gridDim.x - 1) {
+        atomicExch(&ctl[CTL_NEXT], 0u);
+        atomicExch(&ctl[CTL_DONE], 0u);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_step_bf16(const StepHead *h, const StepQ *qs, uint32_t *ctl, uint64_t *tpart,
+                            const Model &m, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_bf16, dim3(grid), dim3(NT), 0, st, h, qs, ctl, tpart, m.d_bf16);
+    return hipGetLastError();
+}
+
+}  // namespace cm

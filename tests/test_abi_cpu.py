@@ -70,3 +70,53 @@ def test_binding_refuses_wrong_parameter_count(cm):
     import numpy as np
     with pytest.raises(ValueError):
         cm.cm_model_create(np.zeros(10, np.float32))
+
+
+def test_step_arguments_are_rejected_before_device_work(cm):
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    good = _lib.cm_step_desc(4, 64, 1024, 32, 2)
+    assert L.cm_step_create(None, _lib.CM_BF16, ctypes.byref(good), ctypes.byref(h)) == _lib.CM_EINVAL
+    # a model handle is only read after the arguments have been checked
+    fake = ctypes.c_void_p(16)
+    assert L.cm_step_create(fake, _lib.CM_FP32, ctypes.byref(good), ctypes.byref(h)) == _lib.CM_EUNSUPPORTED
+    for bad in (_lib.cm_step_desc(0, 64, 1024, 32, 2),       # no queries
+                _lib.cm_step_desc(257, 64, 1024, 32, 2),     # above CM_STEP_MAX_QUERIES
+                _lib.cm_step_desc(4, 64, 1024, 257, 2),      # k above CM_MAX_K
+                _lib.cm_step_desc(4, 64, 1024, 32, 0),       # no slot
+                _lib.cm_step_desc(4, 64, 1024, 32, 9)):      # too many slots
+        assert L.cm_step_create(fake, _lib.CM_BF16, ctypes.byref(bad), ctypes.byref(h)) == _lib.CM_EINVAL
+    assert L.cm_step_run(None, None, None, 8, None, None, None, None) == _lib.CM_EINVAL
+    assert L.cm_step_destroy(None) == _lib.CM_EINVAL
+    cfg = _lib.cm_step_config(0, 1, 1)
+    assert L.cm_step_set_config(None, ctypes.byref(cfg)) == _lib.CM_EINVAL
+    assert L.cm_step_get_config(None, ctypes.byref(cfg)) == _lib.CM_EINVAL
+    assert L.cm_step_autotune(None, None, None, 8, None, None, None, None, 5, None, None) == _lib.CM_EINVAL
+
+
+def test_server_arguments_are_rejected_before_device_work(cm):
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)
+    good = dict(precision=_lib.CM_BF16, k=32, arena_bytes=1 << 30, max_slots=2, max_pending=64,
+                max_sessions=8, max_stages=128, max_batch_queries=16, max_batch_cands=1 << 16)
+    assert L.cm_server_create(None, ctypes.byref(_lib.cm_server_cfg(**good)), ctypes.byref(h)) == _lib.CM_EINVAL
+    assert L.cm_server_create(fake, None, ctypes.byref(h)) == _lib.CM_EINVAL
+    assert L.cm_server_create(fake, ctypes.byref(_lib.cm_server_cfg(**{**good, "precision": _lib.CM_FP32})),
+                              ctypes.byref(h)) == _lib.CM_EUNSUPPORTED
+    for bad in ({"k": 0}, {"k": 257}, {"max_slots": 0}, {"max_slots": 9}, {"max_pending": 0},
+                {"max_batch_queries": 257}, {"max_batch_cands": 0}, {"arena_bytes": 0}):
+        cfg = _lib.cm_server_cfg(**{**good, **bad})
+        assert L.cm_server_create(fake, ctypes.byref(cfg), ctypes.byref(h)) == _lib.CM_EINVAL, bad
+    assert L.cm_server_destroy(None) == _lib.CM_EINVAL
+    sid = ctypes.c_int32()
+    assert L.cm_session_open(None, None, 4, ctypes.byref(sid)) == _lib.CM_EINVAL
+    assert L.cm_session_close(None, 0) == _lib.CM_EINVAL
+    t = ctypes.c_uint64()
+    assert L.cm_serve_submit(None, 0, None, ctypes.byref(t)) == _lib.CM_EINVAL
+    assert L.cm_serve_poll(None, 1, None) == _lib.CM_EINVAL
+    assert L.cm_serve_wait(None, 1, 10, None) == _lib.CM_EINVAL
+    assert L.cm_server_get_stats(None, None) == _lib.CM_EINVAL
+    assert L.cm_server_reset_stats(None) == _lib.CM_EINVAL

@@ -1,0 +1,252 @@
+"""The serving loop (cm_server_*, cm_session_*, cm_serve_*) through the C ABI.
+
+Every request's beam must equal, bit for bit, the same query evaluated alone
+(cm_eval_batch CM_BF16 + cm_topk_per_query), whatever micro-batch it was
+admitted into and whatever ran beside it on the device.
+"""
+import numpy as np
+import pytest
+
+from synth import Query, draw_query, model_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2012_07145_amd as cm
+    return cm
+
+
+@pytest.fixture(scope="module")
+def model(cm):
+    m = cm.cm_model_create(model_params(bias=True))
+    yield m
+    m.close()
+
+
+def _alone(cm, model, q, k):
+    import torch
+    batch, cost = cm.pack_queries([q], "bf16")
+    ws = cm.cm_workspace_create(1, q.n_stages, max(1, q.n_cands), max(1, q.n_stages * q.n_cands), k)
+    cm.cm_eval_batch(model, "bf16", batch, ws, cost)
+    idx = torch.empty(k, dtype=torch.int32, device="cuda")
+    val = torch.empty(k, dtype=torch.float32, device="cuda")
+    cm.cm_topk_per_query(cost, batch, k, ws, idx, val)
+    torch.cuda.synchronize()
+    ws.close()
+    return idx.cpu().numpy(), val.cpu().numpy()
+
+
+def _device_inputs(q):
+    """bf16 schedule features and float32 terms of a query, on the device."""
+    import torch
+    sched = torch.from_numpy(np.ascontiguousarray(q.sched, np.float32).ravel()).cuda()
+    sched = sched.to(torch.bfloat16)
+    terms = torch.from_numpy(np.ascontiguousarray(q.terms, np.float32).ravel()).cuda()
+    if sched.numel() == 0:
+        sched = torch.zeros(8, dtype=torch.bfloat16, device="cuda")
+        terms = torch.zeros(4, dtype=torch.float32, device="cuda")
+    return sched, terms
+
+
+def _same(a, b):
+    return np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32))
+
+
+def _sessions(cm, srv, rng, n, smax=120):
+    out = []
+    for _ in range(n):
+        S = int(np.floor(np.exp(rng.uniform(np.log(3), np.log(smax + 1)))))
+        pipe = draw_query(rng, S, 0).pipe
+        out.append((srv.session_open(pipe), pipe))
+    return out
+
+
+def test_serve_results_equal_alone(cm, model):
+    """Many requests from 12 sessions, submitted at once: continuous batching
+    into micro-batches on 3 slots; every beam equals the query alone, and the
+    session's device-resident beam is its latest result."""
+    rng = np.random.default_rng(61)
+    k = 32
+    srv = cm.cm_server_create(model, k=k, max_slots=3, max_sessions=16, max_batch_queries=8,
+                              max_batch_cands=1 << 15)
+    sess = _sessions(cm, srv, rng, 12)
+    reqs = []
+    for r in range(60):
+        sid, pipe = sess[int(rng.integers(len(sess)))]
+        S = pipe.shape[0]
+        base = draw_query(rng, S, int(rng.integers(0, 3000)))
+        q = Query(pipe, base.sched, base.terms)
+        kk = int(rng.integers(1, k + 1))
+        sched, terms = _device_inputs(q)
+        reqs.append([None, sid, q, kk, sched, terms])
+    # the first ten one by one, the rest queued together (so that the worker
+    # finds many requests waiting and batches them)
+    for r in reqs[:10]:
+        r[0] = srv.submit(r[1], r[2].n_cands, r[4], r[5], r[3])
+    for kk in sorted({r[3] for r in reqs[10:]}):
+        part = [r for r in reqs[10:] if r[3] == kk]
+        ts = srv.submit_batch([r[1] for r in part], [r[2].n_cands for r in part],
+                              [r[4].data_ptr() for r in part], [r[5].data_ptr() for r in part], kk)
+        for r, t in zip(part, ts):
+            r[0] = int(t)
+    last = {}
+    for t, sid, q, kk, _, _ in reqs:
+        idx, val, (ts, ta, td) = srv.wait(t, 20000)
+        ri, rv = _alone(cm, model, q, kk)
+        assert np.array_equal(idx, ri[:kk]) and _same(val, rv[:kk]), (t, q.n_stages, q.n_cands)
+        assert ts <= ta <= td
+        if sid not in last or td >= last[sid][0]:
+            last[sid] = (td, q)
+    # session beams: requests of one session complete in submission order
+    for sid, (td, q) in last.items():
+        bi, bv = srv.session_beam(sid, k)
+        ri, rv = _alone(cm, model, q, k)
+        assert np.array_equal(bi, ri) and _same(bv, rv), sid
+    st = srv.stats()
+    assert st["completed"] == 60 and st["submitted"] == 60
+    assert st["micro_batches"] < 50  # requests were batched
+    assert st["queue_depth"] == 0 and st["in_flight"] == 0 and st["arena_in_use"] == 0
+    assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
+    assert st["kernel_us"] > 0 and st["kernel_bytes"] > 0
+    srv.close()
+
+
+def test_serve_arena_admission(cm, model):
+    """An arena that holds one request at a time: everything still completes,
+    in submission order, and the arena is never exceeded."""
+    rng = np.random.default_rng(62)
+    k = 16
+    S, N = 20, 1000
+    need = S * N * 112 + N * 4 + k * 8
+    srv = cm.cm_server_create(model, k=k, arena_bytes=need + need // 2, max_slots=4,
+                              max_sessions=8, max_batch_queries=8)
+    sess = [(srv.session_open(draw_query(rng, S, 0).pipe), None) for _ in range(6)]
+    reqs = []
+    for r in range(18):
+        sid = sess[r % 6][0]
+        q = draw_query(rng, S, N)
+        sched, terms = _device_inputs(q)
+        reqs.append((srv.submit(sid, N, sched, terms, k), sched, terms))
+    done = [srv.wait(t, 20000)[2] for t, _, _ in reqs]
+    admits = [d[1] for d in done]
+    assert admits == sorted(admits)
+    st = srv.stats()
+    assert st["completed"] == 18 and st["arena_high_water"] <= need + need // 2
+    assert st["micro_batches"] == 18
+    srv.close()
+
+
+def test_serve_session_close_and_errors(cm, model):
+    import torch
+    from paper_2012_07145_amd import _lib
+    rng = np.random.default_rng(63)
+    k = 8
+    srv = cm.cm_server_create(model, k=k, arena_bytes=64 << 20, max_slots=1, max_sessions=2,
+                              max_stages=64, max_batch_queries=4, max_batch_cands=50000)
+    pipe = draw_query(rng, 64, 0).pipe
+    sid = srv.session_open(pipe)
+    sid2 = srv.session_open(draw_query(rng, 3, 0).pipe)
+    with pytest.raises(cm.CmError) as e:
+        srv.session_open(pipe)
+    assert e.value.status == _lib.CM_EAGAIN
+    with pytest.raises(cm.CmError) as e:
+        srv.session_open(draw_query(rng, 65, 0).pipe)
+    assert e.value.status == _lib.CM_E2BIG
+    bi, bv = srv.session_beam(sid, k)
+    assert np.all(bi == -1) and np.all(np.isposinf(bv))
+    q = draw_query(rng, 64, 2000)
+    sched, terms = _device_inputs(Query(pipe, q.sched, q.terms))
+    with pytest.raises(cm.CmError) as e:
+        srv.submit(sid, 2000, sched, terms, k + 1)
+    assert e.value.status == _lib.CM_EINVAL
+    with pytest.raises(cm.CmError) as e:
+        srv.submit(sid, 20000, sched, terms, k)  # larger than the arena
+    assert e.value.status == _lib.CM_E2BIG
+    with pytest.raises(cm.CmError) as e:
+        srv.submit(7, 2000, sched, terms, k)
+    assert e.value.status == _lib.CM_ENOTFOUND
+    with pytest.raises(cm.CmError) as e:
+        srv.poll(12345)
+    assert e.value.status == _lib.CM_ENOTFOUND
+    # several beam steps of one session: at most one is admitted at a time,
+    # so closing the session cancels the rest or lets them finish
+    tickets = [srv.submit(sid, 2000, sched, terms, k) for _ in range(4)]
+    srv.session_close(sid)
+    outcomes = []
+    for t in tickets:
+        try:
+            srv.wait(t, 20000)
+            outcomes.append("ok")
+        except cm.CmError as err:
+            assert err.status == _lib.CM_ECANCELED
+            outcomes.append("canceled")
+    assert outcomes[0] == "ok" or outcomes.count("canceled") >= 1
+    # finished and canceled tickets are released
+    with pytest.raises(cm.CmError) as e:
+        srv.poll(tickets[0])
+    assert e.value.status == _lib.CM_ENOTFOUND
+    with pytest.raises(cm.CmError) as e:
+        srv.submit(sid, 2000, sched, terms, k)
+    assert e.value.status == _lib.CM_ENOTFOUND
+    # the session slot is free again once nothing of it is in flight
+    sid3 = srv.session_open(pipe)
+    t = srv.submit(sid3, 2000, sched, terms, k)
+    idx, val, _ = srv.wait(t, 20000)
+    ri, rv = _alone(cm, model, Query(pipe, q.sched, q.terms), k)
+    assert np.array_equal(idx, ri) and _same(val, rv)
+    srv.session_close(sid2)
+    torch.cuda.synchronize()
+    srv.close()
+
+
+def test_serve_empty_and_tiny_requests(cm, model):
+    rng = np.random.default_rng(64)
+    k = 8
+    srv = cm.cm_server_create(model, k=k, max_slots=2, max_sessions=4)
+    pipe = draw_query(rng, 1, 0).pipe
+    sid = srv.session_open(pipe)
+    for n in (0, 1, 7, 8, 9):
+        q = draw_query(rng, 1, n)
+        q = Query(pipe, q.sched, q.terms)
+        sched, terms = _device_inputs(q)
+        idx, val, _ = srv.wait(srv.submit(sid, n, sched, terms, k), 20000)
+        ri, rv = _alone(cm, model, q, k)
+        assert np.array_equal(idx, ri) and _same(val, rv), n
+        assert np.all(idx[n:] == -1)
+    srv.close()
+
+
+def test_serve_submit_batch_and_wait_all(cm, model):
+    """One call queues a beam step of every session; one call waits for all.
+    Two rounds are queued at once: a session's second request waits for its
+    first (one beam step of a session at a time)."""
+    rng = np.random.default_rng(65)
+    k = 32
+    srv = cm.cm_server_create(model, k=k, max_slots=2, max_sessions=32, max_batch_queries=16)
+    sess = _sessions(cm, srv, rng, 24)
+    rounds = []
+    for r in range(2):
+        qs, keep = [], []
+        for sid, pipe in sess:
+            base = draw_query(rng, pipe.shape[0], int(rng.integers(16, 1500)))
+            q = Query(pipe, base.sched, base.terms)
+            sched, terms = _device_inputs(q)
+            qs.append(q)
+            keep.append((sched, terms))
+        t = srv.submit_batch([s for s, _ in sess], [q.n_cands for q in qs],
+                             [a.data_ptr() for a, _ in keep], [b.data_ptr() for _, b in keep], k)
+        rounds.append((t, qs, keep))
+    for t, _, _ in rounds:
+        srv.wait_all(t, 30000)
+    st = srv.stats()
+    assert st["completed"] == 48 and st["in_flight"] == 0 and st["queue_depth"] == 0
+    # the second round ran after the first for every session
+    for (sid, _), q in zip(sess, rounds[1][1]):
+        bi, bv = srv.session_beam(sid, k)
+        ri, rv = _alone(cm, model, q, k)
+        assert np.array_equal(bi, ri) and _same(bv, rv), sid
+    srv.close()
