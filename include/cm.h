@@ -283,8 +283,9 @@ cm_status cm_step_autotune(cm_step *step, const cm_batch *batch, const float *U,
 
 /* Kernel-only GPU time, in microseconds, of the step's most recent run (the
  * persistent evaluation-and-selection kernel alone, without the descriptor
- * copy or the hoist), from HIP events recorded around that kernel on the
- * run's stream.  Waits for that run to finish.  Errors: CM_EINVAL,
+ * copy or the hoist): from the first of its workgroups to start to the last
+ * to finish, read from the GPU's constant-rate real-time counter (100 MHz)
+ * by the kernel itself.  Waits for that run to finish.  Errors: CM_EINVAL,
  * CM_ENOTFOUND (the step has not run), CM_EDEVICE. */
 cm_status cm_step_kernel_time(cm_step *step, float *us);
 

@@ -139,8 +139,14 @@ struct StepHead {
 // Control words of a step, zero between steps (the step kernel leaves them
 // zero when it ends): task queue head, exit count, per-query and per-tile
 // arrival counts.
+// CTL_CLK: running (first start, last end) of the launch's workgroups and
+// CTL_CLKOUT: the last finished launch's pair, as 64-bit words of the
+// constant-rate real-time counter (100 MHz).
 constexpr int CTL_NEXT = 0;
+constexpr int CTL_CLK = 16;
+constexpr int CTL_CLKOUT = 24;
 constexpr int CTL_DONE = 32;
+constexpr double CLOCK_MHZ = 100.0;
 constexpr int CTL_QCNT = 64;
 constexpr int CTL_TCNT = CTL_QCNT + STEP_MAX_QUERIES;
 
@@ -167,6 +173,9 @@ const cm_step_desc &step_caps(const cm_step *S);
 // Kernel-only GPU time (microseconds) of the step's most recent launch,
 // waiting for it if it is still running.
 cm_status step_kernel_us(cm_step *S, float *us);
+// Device address of the (first start, last end) clock pair that the step's
+// most recent launch leaves behind (two uint64 words; see CTL_CLKOUT).
+const uint64_t *step_clock(const cm_step *S);
 
 // Kernel launchers (one per translation unit).
 hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, const float *pipe,

@@ -53,6 +53,7 @@ struct SlotState {
     float *d_val = nullptr;
     int32_t *h_idx = nullptr;  // pinned
     float *h_val = nullptr;    // pinned
+    uint64_t *h_clk = nullptr; // pinned: the step kernel's (first start, last end)
     hipEvent_t done = nullptr;
     bool busy = false;
     int32_t kb = 0;            // beam width of the micro-batch (the server's k)
@@ -123,6 +124,7 @@ void free_server(cm_server *V)
         if (s.d_val) (void)hipFree(s.d_val);
         if (s.h_idx) (void)hipHostFree(s.h_idx);
         if (s.h_val) (void)hipHostFree(s.h_val);
+        if (s.h_clk) (void)hipHostFree(s.h_clk);
         if (s.done) (void)hipEventDestroy(s.done);
     }
     if (V->d_U) (void)hipFree(V->d_U);
@@ -157,11 +159,8 @@ void set_fault(cm_server &V, const char *what, hipError_t e)
 // Retire a finished micro-batch (mu held).
 void retire(cm_server &V, SlotState &sl)
 {
-    float kus = 0.f;
-    if (cm::step_kernel_us(sl.step, &kus) == CM_OK) {
-        V.kernel_us += kus;
-        V.kernel_bytes += sl.rows * (cm::FS * 2 + cm::C * 4) + sl.cands * 4;
-    }
+    V.kernel_us += (double)(sl.h_clk[1] - sl.h_clk[0]) / cm::CLOCK_MHZ;
+    V.kernel_bytes += sl.rows * (cm::FS * 2 + cm::C * 4) + sl.cands * 4;
     const double now = us_since(V.t0);
     for (size_t j = 0; j < sl.tickets.size(); ++j) {
         auto it = V.reqs.find(sl.tickets[j]);
@@ -257,6 +256,9 @@ bool admit(cm_server &V, SlotState &sl)
         e = hipMemcpyAsync(sl.h_idx, sl.d_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost, sl.st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.h_val, sl.d_val, nb * sizeof(float), hipMemcpyDeviceToHost, sl.st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl.h_clk, cm::step_clock(sl.step), 2 * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, sl.st);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.st);
     if (e != hipSuccess) set_fault(V, "micro-batch launch", e);
     return true;
@@ -403,6 +405,7 @@ cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_s
         ok = ok && hipMalloc((void **)&s.d_val, nb * 4) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&s.h_idx, nb * 4, 0) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&s.h_val, nb * 4, 0) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&s.h_clk, 16, 0) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess;
         if (ok) {
             const cm_step_desc sd{c.max_batch_queries, 1, c.max_batch_cands, c.k, 1};

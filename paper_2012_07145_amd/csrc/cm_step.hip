@@ -23,7 +23,6 @@ struct Slot {
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // [with hoist]
     int exec_grid[2] = {0, 0};
     hipEvent_t done = nullptr;         // recorded after the slot's last step
-    hipEvent_t k0 = nullptr, k1 = nullptr;  // around the step kernel (timing)
     bool pending = false;
 };
 
@@ -67,8 +66,6 @@ void free_slot(Slot &s)
     for (auto &e : s.exec)
         if (e) (void)hipGraphExecDestroy(e);
     if (s.done) (void)hipEventDestroy(s.done);
-    if (s.k0) (void)hipEventDestroy(s.k0);
-    if (s.k1) (void)hipEventDestroy(s.k1);
     if (s.h_block) (void)hipHostFree(s.h_block);
     if (s.d_block) (void)hipFree(s.d_block);
     if (s.d_ctl) (void)hipFree(s.d_ctl);
@@ -201,11 +198,7 @@ hipError_t issue(const cm_step &S, Slot &sl, bool hoist, size_t bytes, hipStream
     if (e != hipSuccess) return e;
     if (hoist && (e = launch_step_hoist(h, qs, S.model->m, hoist_grid(S), st)) != hipSuccess)
         return e;
-    if ((e = hipEventRecord(sl.k0, st)) != hipSuccess) return e;
-    if ((e = launch_step_bf16(h, qs, sl.d_ctl, sl.d_tpart, S.model->m, grid_of(S), st)) !=
-        hipSuccess)
-        return e;
-    return hipEventRecord(sl.k1, st);
+    return launch_step_bf16(h, qs, sl.d_ctl, sl.d_tpart, S.model->m, grid_of(S), st);
 }
 
 cm_status get_exec(cm_step &S, Slot &sl, bool hoist, hipGraphExec_t *out)
@@ -329,11 +322,17 @@ cm_status step_kernel_us(cm_step *S, float *us)
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->last < 0) return fail(CM_ENOTFOUND, "the step has not run yet");
     Slot &sl = S->slot[S->last];
-    CM_HIP(hipEventSynchronize(sl.k1));
-    float ms = 0.f;
-    CM_HIP(hipEventElapsedTime(&ms, sl.k0, sl.k1));
-    *us = ms * 1000.f;
+    CM_HIP(hipEventSynchronize(sl.done));
+    uint64_t clk[2];
+    CM_HIP(hipMemcpy(clk, sl.d_ctl + CTL_CLKOUT, sizeof clk, hipMemcpyDeviceToHost));
+    *us = (float)((double)(clk[1] - clk[0]) / CLOCK_MHZ);
     return CM_OK;
+}
+
+const uint64_t *step_clock(const cm_step *S)
+{
+    const int s = S->last < 0 ? 0 : S->last;
+    return reinterpret_cast<const uint64_t *>(S->slot[s].d_ctl + CTL_CLKOUT);
 }
 
 }  // namespace cm
@@ -394,14 +393,16 @@ cm_status cm_step_create(const cm_model *model, cm_precision prec, const cm_step
         ok = ok && hipMalloc((void **)&sl.d_U, (size_t)d->max_stages * H * sizeof(float)) ==
                        hipSuccess;
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
-        ok = ok && hipEventCreate(&sl.k0) == hipSuccess && hipEventCreate(&sl.k1) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_step(S);
             return fail(CM_ENOMEM, "step allocation failed");
         }
         std::memset(sl.h_block, 0, S->block_bytes);
-        if (hipMemset(sl.d_ctl, 0, ctl_words(*S) * sizeof(uint32_t)) != hipSuccess) {
+        const uint64_t clk_init[2] = {~0ull, 0ull};  // (first start, last end)
+        if (hipMemset(sl.d_ctl, 0, ctl_words(*S) * sizeof(uint32_t)) != hipSuccess ||
+            hipMemcpy(sl.d_ctl + CTL_CLK, clk_init, sizeof clk_init, hipMemcpyHostToDevice) !=
+                hipSuccess) {
             free_step(S);
             return fail(CM_EDEVICE, "step initialisation failed");
         }

@@ -3,7 +3,7 @@
 // one launch whose shape never depends on the batch.
 //
 // A fixed grid of workgroups (8 waves each) takes tasks from a device-wide
-// queue (one atomic add per task, fetched one task ahead).  A task is `gpt`
+// queue (one atomic add per task, taken when the previous task ends).  A task is `gpt`
 // consecutive row-tile groups of one query, evaluated exactly as the
 // per-call kernel does (eval_bf16.h), so the costs are bit-identical to it.
 // Tasks never straddle a selection tile of TOPK_TILE candidates; the
@@ -65,22 +65,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const int nq = h->nq, ntasks = h->ntasks, k = h->k, gpt = h->gpt;
     uint32_t *qcnt = ctl + CTL_QCNT;
     uint32_t *tcnt = ctl + CTL_TCNT;
+    unsigned long long *clk = reinterpret_cast<unsigned long long *>(ctl + CTL_CLK);
 
     for (int j = tid; j < nq; j += NT) task0[j] = qs[j].task0;
-    if (tid == 0) s_next = (int)atomicAdd(&ctl[CTL_NEXT], 1u);
+    if (tid == 0) {
+        atomicMin(&clk[0], (unsigned long long)__builtin_amdgcn_s_memrealtime());
+        s_next = (int)atomicAdd(&ctl[CTL_NEXT], 1u);
+    }
     const Pairs kp = make_pairs();
     __syncthreads();
     int t = s_next;
-    // The arrival of a task at its selection tile is counted when the task
-    // ends, and its result is looked at only when the next task ends (or
-    // when the workgroup leaves), so no wave waits for the count: the tile
-    // of an earlier task (q_prev, tile_prev) is selected one task later.
-    uint32_t arrived = 0;    // thread 0: the count before this workgroup's arrival
-    uint32_t need = 0;       // thread 0: arrivals that complete that tile
-    int q_prev = -1, tile_prev = 0;
     while (t < ntasks) {
-        __syncthreads();  // every thread has read s_next
-        if (tid == 0) s_next = (int)atomicAdd(&ctl[CTL_NEXT], 1u);  // next task, fetched early
         // the query of task t: the last q with task0[q] <= t
         int lo = 0, hi = nq - 1;
         while (lo < hi) {
@@ -109,38 +104,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                 __syncthreads();  // the group's LDS is reused by the next group
             }
         }
-        // this task's costs (coherent stores) are complete before it arrives
+        // this task's costs (coherent stores) have completed before it counts
+        // itself at its selection tile; the next task is taken only now, so
+        // that the queue hands work to whichever workgroup is free first
         const int tpt = TOPK_TILE / (group_rows * gpt);  // tasks per tile
         const int tile = tq / tpt;
         wait_stores();
         __syncthreads();
         if (tid == 0) {
-            s_tail = q_prev >= 0 && arrived == need - 1;  // the previous task's arrival
-            need = (uint32_t)min(tpt, D.ntasks - tile * tpt);
-            arrived = atomicAdd(&tcnt[D.tile0 + tile], 1u);  // looked at one task later
+            const uint32_t need = (uint32_t)min(tpt, D.ntasks - tile * tpt);
+            const uint32_t next = atomicAdd(&ctl[CTL_NEXT], 1u);
+            const uint32_t arrived = atomicAdd(&tcnt[D.tile0 + tile], 1u);
+            s_next = (int)next;
+            s_tail = arrived == need - 1;
         }
         __syncthreads();
         if (s_tail) {
-            if (tid == 0) atomicExch(&tcnt[qs[q_prev].tile0 + tile_prev], 0u);
-            select_tile(qs[q_prev], q_prev, tile_prev, k, qcnt, tpart, tsh, s_query_last);
+            if (tid == 0) atomicExch(&tcnt[D.tile0 + tile], 0u);
+            select_tile(D, q, tile, k, qcnt, tpart, tsh, s_query_last);
         }
-        q_prev = q;
-        tile_prev = tile;
-        __syncthreads();  // s_next is written; the selection's LDS is free
         t = s_next;
+        __syncthreads();  // s_next and s_tail are read; the selection's LDS is free
     }
-    // the last arrival of this workgroup
-    if (tid == 0) s_tail = q_prev >= 0 && arrived == need - 1;
-    __syncthreads();
-    if (s_tail) {
-        if (tid == 0) atomicExch(&tcnt[qs[q_prev].tile0 + tile_prev], 0u);
-        select_tile(qs[q_prev], q_prev, tile_prev, k, qcnt, tpart, tsh, s_query_last);
-    }
-    // the last workgroup to leave resets the queue for the next launch: every
-    // other workgroup has made its final queue fetch before counting itself
-    if (tid == 0 && atomicAdd(&ctl[CTL_DONE], 1u) == gridDim.x - 1) {
-        atomicExch(&ctl[CTL_NEXT], 0u);
-        atomicExch(&ctl[CTL_DONE], 0u);
+    // the last workgroup to leave resets the queue for the next launch (every
+    // other workgroup has made its final queue fetch before counting itself)
+    // and publishes the launch's clock pair
+    if (tid == 0) {
+        atomicMax(&clk[1], (unsigned long long)__builtin_amdgcn_s_memrealtime());
+        wait_stores();
+        if (atomicAdd(&ctl[CTL_DONE], 1u) == gridDim.x - 1) {
+            unsigned long long *out = reinterpret_cast<unsigned long long *>(ctl + CTL_CLKOUT);
+            store_shared(&out[0], atomicExch(&clk[0], ~0ull));
+            store_shared(&out[1], atomicExch(&clk[1], 0ull));
+            atomicExch(&ctl[CTL_NEXT], 0u);
+            atomicExch(&ctl[CTL_DONE], 0u);
+        }
     }
 }
 

@@ -11,9 +11,9 @@
 // One workgroup of NT threads selects over a tile of up to TOPK_TILE
 // candidates (TOPK_TILE / NT keys per thread, element e = j*NT + thread):
 //   1. every thread takes the minimum of its keys; the k-th smallest of these
-//      NT minima (found by one wave with a bitwise radix search on ballots)
-//      is a threshold T with at least k keys <= T (the k minima themselves),
-//      and for unordered costs only slightly more than k;
+//      NT minima (a bitonic sort of the minima across the workgroup) is a
+//      threshold T with at least k keys <= T (the k minima themselves), and
+//      for unordered costs only slightly more than k;
 //   2. keys <= T are compacted into LDS with one atomic per wave and key slot;
 //   3. each compacted key is placed by counting the compacted keys below it;
 //      keys placed at rank < k are the k best, already in order.
@@ -61,65 +61,42 @@ struct TopkShared {
 
 __device__ inline uint32_t wave_count(bool p) { return (uint32_t)__popcll(__ballot(p)); }
 
-// ---------------------------------------------------------------- one wave
-// The value v such that the rank-th (1-based) smallest selected value is v;
-// rank becomes the rank among the selected values equal to v.
-template <int NV>
-__device__ uint32_t wave_radix(const uint32_t (&val)[NV], const bool (&sel)[NV], uint32_t &rank)
+// ---------------------------------------------------------------- sorting
+__device__ inline uint64_t shfl_xor64(uint64_t v, int mask)
 {
-    uint32_t a = 0xffffffffu, o = 0;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (sel[j]) {
-            a &= val[j];
-            o |= val[j];
-        }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        a &= (uint32_t)__shfl_xor((int)a, d);
-        o |= (uint32_t)__shfl_xor((int)o, d);
-    }
-    const uint32_t diff = a ^ o;
-    if (diff == 0) return a;
-    const int hb = 31 - __clz(diff);
-    uint32_t prefix = a & ~((2u << hb) - 1u);  // bits above hb are shared
-    for (int b = hb; b >= 0; --b) {
-        const uint32_t hmask = ~((2u << b) - 1u);
-        uint32_t c = 0;
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            c += wave_count(sel[j] && ((val[j] ^ prefix) & hmask) == 0 && !((val[j] >> b) & 1u));
-        if (c < rank) {
-            rank -= c;
-            prefix |= 1u << b;
-        }
-    }
-    return prefix;
+    const int lo = __shfl_xor((int)(uint32_t)v, mask);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// Threshold with exactly `rank` selected keys <= it (1-based rank, at least
-// `rank` keys selected): the rank-th smallest key, or the largest possible
-// key with the same cost image when all keys tying there are needed.
-template <int NV>
-__device__ uint64_t wave_threshold(const uint64_t (&key)[NV], uint32_t rank)
+// Ascending bitonic sort of one key per thread across the NT-thread
+// workgroup: thread t returns the key of rank t.  Pairs closer than a wave
+// exchange by shuffles; farther ones through x (NT keys of LDS).
+template <int NT>
+__device__ uint64_t block_sort1(uint64_t key, uint64_t *x)
 {
-    uint32_t hi[NV], lo[NV];
-    bool sel[NV], eq[NV];
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        hi[j] = (uint32_t)(key[j] >> 32);
-        lo[j] = (uint32_t)key[j];
-        sel[j] = key[j] != SENT;
-    }
-    const uint32_t thi = wave_radix(hi, sel, rank);
-    uint32_t neq = 0;
+    for (int size = 2; size <= NT; size <<= 1) {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        eq[j] = sel[j] && hi[j] == thi;
-        neq += wave_count(eq[j]);
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            uint64_t other;
+            if (stride >= 64) {
+                x[t] = key;
+                __syncthreads();
+                other = x[t ^ stride];
+                __syncthreads();
+            } else {
+                other = shfl_xor64(key, stride);
+            }
+            const bool up = (t & size) == 0;       // this run ascends
+            const bool lower = (t & stride) == 0;  // t is the first of its pair
+            const uint64_t mn = key < other ? key : other;
+            const uint64_t mx = key < other ? other : key;
+            key = lower == up ? mn : mx;
+        }
     }
-    const uint32_t tlo = neq > rank ? wave_radix(lo, eq, rank) : 0xffffffffu;
-    return ((uint64_t)thi << 32) | tlo;
+    return key;
 }
 
 // ---------------------------------------------------------------- workgroup
@@ -229,16 +206,10 @@ __device__ int tile_select(const uint64_t (&key)[TopkShared<NT>::PER], int nvali
         uint64_t m = key[0];
 #pragma unroll
         for (int j = 1; j < PER; ++j) m = key[j] < m ? key[j] : m;
-        sh.mins[t] = m;
-        __syncthreads();
-        if (t < 64) {
-            uint64_t v[NT / 64];
-#pragma unroll
-            for (int j = 0; j < NT / 64; ++j) v[j] = sh.mins[j * 64 + lane];
-            // min(nvalid, NT) >= k + 1 threads hold a real key
-            const uint64_t thr = wave_threshold(v, (uint32_t)k);
-            if (t == 0) sh.thr = thr;
-        }
+        // min(nvalid, NT) >= k + 1 threads hold a real key, so the minimum of
+        // rank k - 1 is a real key
+        m = block_sort1<NT>(m, sh.mins);
+        if (t == k - 1) sh.thr = m;
     }
     __syncthreads();
     if (nvalid > k) T = sh.thr;
