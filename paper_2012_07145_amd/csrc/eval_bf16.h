@@ -113,8 +113,12 @@ __device__ inline void log_split4(uint2 raw, bf16x8 &hi, bf16x8 &lo, const Pairs
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
-// ReLU that lets a NaN through, like the oracle
-__device__ inline float relu(float x) { return x < 0.f ? 0.f : x; }
+// max(x, 0) on the bit pattern (negative floats are negative integers): one
+// instruction.  It maps a NaN with the sign bit set to 0; stage_math restores
+// NaN propagation by testing one hidden pre-activation per stage, since an
+// invalid input makes every hidden unit of its candidate NaN (each sums every
+// feature times a weight, and 0 * NaN is NaN).
+__device__ inline float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 __device__ inline void kahan_add(float &s, float &c, float v)
 {
@@ -145,14 +149,27 @@ struct StageIn {
     float4 t;
 };
 
-// xs, ts: the stage's rows (uniform); xo, x2o, to: this lane's byte offsets
-__device__ inline void load_stage(StageIn &in, const char *xs, const char *ts, uint32_t xo,
-                                  uint32_t x2o, uint32_t to)
+// Buffer descriptor over n bytes at p (raw, untyped dword access; loads at
+// or past n bytes return 0).
+__device__ inline __amdgpu_buffer_rsrc_t buffer_over(const void *p, uint32_t n)
 {
-    in.x0 = *reinterpret_cast<const uint4 *>(xs + xo);
-    in.x1 = *reinterpret_cast<const uint4 *>(xs + xo + 32);
-    in.x2 = *reinterpret_cast<const uint2 *>(xs + x2o);
-    in.t = *reinterpret_cast<const float4 *>(ts + to);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n,
+                                             0x00020000);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// One stage's loads: xsoff, tsoff = byte offsets of the stage's rows
+// (uniform); xo, x2o, to = this lane's byte offsets inside the stage.
+__device__ inline void load_stage(StageIn &in, __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t tr,
+                                  uint32_t xsoff, uint32_t tsoff, uint32_t xo, uint32_t x2o,
+                                  uint32_t to)
+{
+    in.x0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo, xsoff, 0));
+    in.x1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo + 32, xsoff, 0));
+    in.x2 = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(xr, x2o, xsoff, 0));
+    in.t = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, 0));
 }
 
 struct Weights {
@@ -200,6 +217,8 @@ __device__ __forceinline__ void stage_math(const StageIn &in, const float4 *us, 
     acc = mfma(w.A1l[2], bh, acc);
     acc = mfma(w.A1h[2], bl, acc);
 
+    const bool invalid = acc[0] != acc[0];  // NaN: an input outside log1p's domain
+
     // coefficient layer (output registers 0..3 are the 8 real outputs); its
     // bias is added after the products
     f32x16 acc2;
@@ -222,6 +241,7 @@ __device__ __forceinline__ void stage_math(const StageIn &in, const float4 *us, 
     v = fmaf(relu(acc2[1] + w.b2v[1]), in.t.y, v);
     v = fmaf(relu(acc2[2] + w.b2v[2]), in.t.z, v);
     v = fmaf(relu(acc2[3] + w.b2v[3]), in.t.w, v);
+    if (invalid) v = __builtin_nanf("");
     kahan_add(sum, comp, add_halves(v));
 }
 
@@ -283,11 +303,15 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
     const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
 
-    // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart
-    const int64_t xstep = (int64_t)Q.N * FS * 2;
-    const int64_t tstep = (int64_t)Q.N * C * 4;
-    const char *xs = reinterpret_cast<const char *>(Q.x) + s0 * xstep;
-    const char *ts = reinterpret_cast<const char *>(Q.t) + s0 * tstep;
+    // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart;
+    // a query's arrays stay below 4 GB (S <= 2^16 stages of N <= 2^16 rows is
+    // far beyond any workload; the host rejects larger)
+    const uint32_t xstep = (uint32_t)Q.N * FS * 2;
+    const uint32_t tstep = (uint32_t)Q.N * C * 4;
+    const __amdgpu_buffer_rsrc_t xr = buffer_over(Q.x, xstep * (uint32_t)Q.S);
+    const __amdgpu_buffer_rsrc_t tr = buffer_over(Q.t, tstep * (uint32_t)Q.S);
+    uint32_t xsoff = (uint32_t)s0 * xstep;
+    uint32_t tsoff = (uint32_t)s0 * tstep;
     const uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
     const uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
     const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
@@ -300,27 +324,25 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
         // two register buffers alternate so that a stage's loads stay in
         // flight during the previous stage's arithmetic without copies
         StageIn A, B;
-        load_stage(A, xs, ts, xo, x2o, to);
+        load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
         for (int s = s0; s < s1; s += 2) {
             if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
             if (s + 1 < s1) {
-                xs += xstep;
-                ts += tstep;
+                xsoff += xstep;
+                tsoff += tstep;
             }
-            load_stage(B, xs, ts, xo, x2o, to);
-            // keep the loads here, ahead of their use (the feature pointers
-            // are not restrict-qualified, so the compiler cannot move them
-            // across this)
+            load_stage(B, xr, tr, xsoff, tsoff, xo, x2o, to);
+            // keep the loads here, ahead of their use
             asm volatile("" ::: "memory");
             stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
             if (s + 1 >= s1) break;
 
             if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
             if (s + 2 < s1) {
-                xs += xstep;
-                ts += tstep;
+                xsoff += xstep;
+                tsoff += tstep;
             }
-            load_stage(A, xs, ts, xo, x2o, to);
+            load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
             asm volatile("" ::: "memory");
             stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
         }
