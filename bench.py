@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--slots", type=int, default=3, help="serving micro-batches in flight")
+    ap.add_argument("--max-batch-queries", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -138,9 +140,9 @@ def main():
     torch.cuda.synchronize()
     in_bytes = sum(S * N * BYTES_PER_ROW_BF16 for S, _, reqs in sess_in for N, _, _ in reqs)
     log(f"{in_bytes / 1e9:.2f} GB of request inputs resident")
-    srv = cm.cm_server_create(model, k=K, arena_bytes=16 << 30, max_slots=3, max_pending=8192,
-                              max_sessions=SESSIONS, max_stages=128, max_batch_queries=128,
-                              max_batch_cands=1 << 19)
+    srv = cm.cm_server_create(model, k=K, arena_bytes=16 << 30, max_slots=args.slots,
+                              max_pending=8192, max_sessions=SESSIONS, max_stages=128,
+                              max_batch_queries=args.max_batch_queries, max_batch_cands=1 << 20)
     sids = [srv.session_open(pipe) for _, pipe, _ in sess_in]
 
     # a step's request j of every session, as pre-marshalled arrays
@@ -353,8 +355,8 @@ def main():
                    "stages": "log-uniform [3, 120] per session",
                    "candidates": "uniform [16, 4096] per query",
                    "inputs_per_session": args.inputs_per_session,
-                   "input_gb": round(in_bytes / 1e9, 2), "slots": 3,
-                   "max_batch_queries": 128},
+                   "input_gb": round(in_bytes / 1e9, 2), "slots": args.slots,
+                   "max_batch_queries": args.max_batch_queries},
         "rows_per_s": rows / wall,
         "latency": latency,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

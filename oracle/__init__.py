@@ -36,6 +36,17 @@ class Oracle:
         L.cmo_eval.argtypes = [_f32p, ctypes.c_int32, ctypes.c_int32, _f32p, _f32p,
                                _f32p, _f64p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_int32]
+        L.cmo_e4m3_decode.restype = ctypes.c_double
+        L.cmo_e4m3_decode.argtypes = [ctypes.c_uint8]
+        L.cmo_e4m3_encode.restype = ctypes.c_uint8
+        L.cmo_e4m3_encode.argtypes = [ctypes.c_double]
+        L.cmo_fp8_scale.restype = ctypes.c_double
+        L.cmo_fp8_scale.argtypes = [ctypes.c_double]
+        L.cmo_eval_fp8.restype = None
+        L.cmo_eval_fp8.argtypes = [_f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.c_int32, _f32p,
+                                   np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"),
+                                   _f32p, _f64p, ctypes.c_int32]
         L.cmo_select.restype = ctypes.c_int32
         L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
         self.L = L
@@ -72,6 +83,28 @@ class Oracle:
             out.append(co)
         return out[0] if len(out) == 1 else tuple(out)
 
+    def e4m3_decode(self, code: int) -> float:
+        return float(self.L.cmo_e4m3_decode(int(code)))
+
+    def e4m3_encode(self, v: float) -> int:
+        return int(self.L.cmo_e4m3_encode(float(v)))
+
+    def fp8_scale(self, amax: float) -> float:
+        return float(self.L.cmo_fp8_scale(float(amax)))
+
+    def eval_query_fp8(self, params, in_scale, act_scale, pipe, codes, terms, *,
+                       nthreads: int = 0):
+        """FP64 predicted runtime of the FP8 form: codes[S][N][40] uint8 are e4m3
+        codes of log1p(x) * in_scale."""
+        params, pipe, terms = _f32(params), _f32(pipe), _f32(terms)
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        S, N = codes.shape[0], codes.shape[1]
+        assert codes.shape == (S, N, 40) and pipe.shape == (S, 56) and terms.shape == (S, N, 8)
+        cost = np.empty(N, np.float64)
+        self.L.cmo_eval_fp8(params, float(in_scale), float(act_scale), S, N, pipe, codes,
+                            terms, cost, int(nthreads))
+        return cost
+
     def select(self, cost, k: int):
         """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""
         cost = np.ascontiguousarray(cost, dtype=np.float64)
@@ -106,3 +139,19 @@ def eval_query(*a, **kw):
 
 def select(cost, k: int):
     return lib().select(cost, k)
+
+
+def eval_query_fp8(*a, **kw):
+    return lib().eval_query_fp8(*a, **kw)
+
+
+def e4m3_encode(v: float) -> int:
+    return lib().e4m3_encode(v)
+
+
+def e4m3_decode(code: int) -> float:
+    return lib().e4m3_decode(code)
+
+
+def fp8_scale(amax: float) -> float:
+    return lib().fp8_scale(amax)

@@ -29,7 +29,15 @@
  *    shared by all candidates of the query;
  *  - the best candidate is the one with the lowest predicted runtime; ties go
  *    to the lower candidate index; -0 equals +0; NaN ranks after +inf.
+ *
+ * The FP8 form (cmo_eval_fp8) is the same model evaluated with the
+ * quantization points of the 8-bit precision form (the paper fixes no
+ * precision; this form is a reading): e4m3 codes of log1p(x) * s_in as
+ * inputs, the schedule embedding folded into the first layer, per-layer
+ * power-of-two weight scales, hidden activations quantized with a given
+ * scale; everything between the quantization points in FP64.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -141,6 +149,129 @@ void cmo_eval(const float *params, int32_t S, int32_t N, const float *pipe,
         }
         cost_out[i] = total;
     }
+    (void)nthreads;
+}
+
+/* ---- FP8 (e4m3) form ---- */
+
+/* OCP 8-bit floating point E4M3: sign, 4 exponent bits (bias 7), 3 mantissa
+ * bits; exponent 0 holds subnormals m * 2^-9; no infinities; exponent 15 with
+ * mantissa 7 is NaN, so the largest finite magnitude is 1.75 * 2^8 = 448. */
+double cmo_e4m3_decode(uint8_t code)
+{
+    const int sign = code >> 7, e = (code >> 3) & 15, m = code & 7;
+    if (e == 15 && m == 7) return NAN;
+    const double v = e == 0 ? ldexp((double)m, -9) : ldexp(1.0 + m / 8.0, e - 7);
+    return sign ? -v : v;
+}
+
+/* Nearest e4m3 value, ties to the even code (the code's last bit is the
+ * mantissa's last bit), magnitudes at or above 448 saturate to 448, NaN maps
+ * to the positive NaN code.  Found by comparing against every finite code. */
+uint8_t cmo_e4m3_encode(double v)
+{
+    if (isnan(v)) return 0x7F;
+    const uint8_t sign = signbit(v) ? 0x80 : 0x00;
+    const double a = fabs(v);
+    if (a >= 448.0) return sign | 0x7E;
+    int best = 0;
+    double bd = INFINITY;
+    for (int c = 0; c <= 0x7E; ++c) {
+        const double d = fabs(cmo_e4m3_decode((uint8_t)c) - a);
+        if (d < bd || (d == bd && (c & 1) == 0)) {
+            bd = d;
+            best = c;
+        }
+    }
+    return (uint8_t)(sign | best);
+}
+
+/* The largest power of two not above 448 / amax (1 when amax is 0). */
+double cmo_fp8_scale(double amax)
+{
+    if (!(amax > 0.0)) return 1.0;
+    int e;
+    frexp(448.0 / amax, &e);
+    return ldexp(1.0, e - 1);
+}
+
+static double q8(double v) { return cmo_e4m3_decode(cmo_e4m3_encode(v)); }
+
+void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
+                  int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
+                  double *cost_out, int32_t nthreads)
+{
+    cmo_params P = split_params(params);
+    /* folded first layer over the schedule features and its bias share */
+    double Wf[H][FS], beta[H], Wq1[H][FS], Wq2[C][H];
+    double amax1 = 0.0, amax2 = 0.0;
+    for (int h = 0; h < H; ++h) {
+        double b = 0.0;
+        for (int e = 0; e < E; ++e) b += (double)P.W1[h * 2 * E + E + e] * (double)P.bs[e];
+        beta[h] = b;
+        for (int f = 0; f < FS; ++f) {
+            double a = 0.0;
+            for (int e = 0; e < E; ++e)
+                a += (double)P.W1[h * 2 * E + E + e] * (double)P.Ws[e * FS + f];
+            Wf[h][f] = a;
+            if (fabs(a) > amax1) amax1 = fabs(a);
+        }
+    }
+    for (int c = 0; c < C; ++c)
+        for (int h = 0; h < H; ++h)
+            if (fabs((double)P.W2[c * H + h]) > amax2) amax2 = fabs((double)P.W2[c * H + h]);
+    const double sw1 = cmo_fp8_scale(amax1), sw2 = cmo_fp8_scale(amax2);
+    for (int h = 0; h < H; ++h)
+        for (int f = 0; f < FS; ++f) Wq1[h][f] = q8(Wf[h][f] * sw1);
+    for (int c = 0; c < C; ++c)
+        for (int h = 0; h < H; ++h) Wq2[c][h] = q8((double)P.W2[c * H + h] * sw2);
+
+    /* per stage: the algorithm embedding's share of the first layer */
+    double *u = (double *)malloc(sizeof(double) * (size_t)(S > 0 ? S : 1) * H);
+    if (!u) return;
+    for (int s = 0; s < S; ++s) {
+        double p[FP], ep[E];
+        for (int f = 0; f < FP; ++f) p[f] = log1p((double)pipe[s * FP + f]);
+        for (int e = 0; e < E; ++e) {
+            double a = (double)P.bp[e];
+            for (int f = 0; f < FP; ++f) a += (double)P.Wp[e * FP + f] * p[f];
+            ep[e] = a;
+        }
+        for (int h = 0; h < H; ++h) {
+            double a = (double)P.b1[h];
+            for (int e = 0; e < E; ++e) a += (double)P.W1[h * 2 * E + e] * ep[e];
+            u[s * H + h] = a + beta[h];
+        }
+    }
+    const double s1 = sw1 * in_scale, s2 = sw2 * act_scale;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int64_t i = 0; i < (int64_t)N; ++i) {
+        double stage_sum = 0.0;
+        for (int64_t s = 0; s < (int64_t)S; ++s) {
+            const int64_t row = s * (int64_t)N + i;
+            const uint8_t *q = codes + row * FS;
+            double hq[H];
+            for (int h = 0; h < H; ++h) {
+                double a = s1 * u[s * H + h];
+                for (int f = 0; f < FS; ++f) a += Wq1[h][f] * cmo_e4m3_decode(q[f]);
+                const double pre = a / s1;
+                hq[h] = q8((pre < 0.0 ? 0.0 : pre) * act_scale); /* ReLU, then quantize */
+            }
+            double v = 0.0;
+            for (int c = 0; c < C; ++c) {
+                double a = 0.0;
+                for (int h = 0; h < H; ++h) a += Wq2[c][h] * hq[h];
+                a = a / s2 + (double)P.b2[c];
+                v += (a < 0.0 ? 0.0 : a) * (double)terms[row * C + c];
+            }
+            stage_sum += v;
+        }
+        cost_out[i] = stage_sum;
+    }
+    free(u);
     (void)nthreads;
 }
 

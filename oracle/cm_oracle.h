@@ -26,6 +26,20 @@ void cmo_eval(const float *params, int32_t S, int32_t N, const float *pipe,
               const float *sched, const float *terms, double *cost_out,
               double *stage_cost_out, double *coef_out, int32_t nthreads);
 
+/* OCP e4m3 codec: decode a code; encode with round-to-nearest (ties to even),
+ * saturation at +-448 and NaN -> 0x7F. */
+double cmo_e4m3_decode(uint8_t code);
+uint8_t cmo_e4m3_encode(double v);
+/* Per-layer scale of the FP8 form: the largest power of two <= 448 / amax. */
+double cmo_fp8_scale(double amax);
+
+/* FP8 form of cmo_eval: codes[S][N][40] are e4m3 codes of log1p(x) * in_scale;
+ * weights quantized per layer (first layer folded: W_1[:, 24:] W_s), hidden
+ * activations quantized as e4m3(ReLU(h) * act_scale); FP64 in between. */
+void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
+                  int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
+                  double *cost_out, int32_t nthreads);
+
 /* The k best candidates: ascending cost, ties by lower index, -0 == +0, NaN
  * last; k > N pads with (-1, +inf).  Returns 0, or <0 on bad sizes / no memory. */
 int32_t cmo_select(const double *cost, int32_t N, int32_t k, int32_t *idx_out,

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from oracle import build as obuild
+from tests import test_oracle_fp8_pins as fp8pins
 from tests import test_oracle_pins as pins
 
 PIN_TESTS = [
@@ -30,6 +31,14 @@ PIN_TESTS = [
     pins.test_select_nan_last_and_padding,
     pins.test_select_brute_force_tiny,
     pins.test_relu_clips_negative_and_passes_nan,
+    fp8pins.test_e4m3_decode_table,
+    fp8pins.test_e4m3_codes_are_ordered_and_round_trip,
+    fp8pins.test_e4m3_encode_rounding_and_saturation,
+    fp8pins.test_fp8_scale_is_largest_power_of_two,
+    fp8pins.test_fp8_form_hand_examples_exact,
+    fp8pins.test_fp8_form_quantizes_hidden_and_inputs,
+    fp8pins.test_fp8_form_invariants,
+    fp8pins.test_fp8_form_close_to_fp64_model,
 ]
 
 # (name, text in cm_oracle.c, replacement)
@@ -54,6 +63,19 @@ MUTANTS = [
     ("padding index 0", "idx_out[j] = -1;", "idx_out[j] = 0;"),
     ("ReLU maps NaN to 0", "h[j] = a < 0.0 ? 0.0 : a;", "h[j] = a > 0.0 ? a : 0.0;"),
     ("descending order", "if (A->key < B->key) return -1;", "if (A->key > B->key) return -1;"),
+    ("e4m3 subnormals scaled by 2^-10", "ldexp((double)m, -9)", "ldexp((double)m, -10)"),
+    ("e4m3 exponent bias 8", "ldexp(1.0 + m / 8.0, e - 7)", "ldexp(1.0 + m / 8.0, e - 8)"),
+    ("e4m3 ties to the larger code", "(d == bd && (c & 1) == 0)", "(d == bd)"),
+    ("e4m3 no saturation", "if (a >= 448.0) return sign | 0x7E;", "if (a >= 480.0) return sign | 0x7F;"),
+    ("fp8 scale rounds up", "return ldexp(1.0, e - 1);", "return ldexp(1.0, e);"),
+    ("fp8 input scale not undone", "const double pre = a / s1;", "const double pre = a / sw1;"),
+    ("fp8 activation scale not undone", "a = a / s2 + (double)P.b2[c];",
+     "a = a / (s2 / act_scale) + (double)P.b2[c];"),
+    ("fp8 hidden activations not quantized", "hq[h] = q8((pre < 0.0 ? 0.0 : pre) * act_scale);",
+     "hq[h] = (pre < 0.0 ? 0.0 : pre) * act_scale;"),
+    ("fp8 inputs decoded as zero", "a += Wq1[h][f] * cmo_e4m3_decode(q[f]);",
+     "a += Wq1[h][f] * cmo_e4m3_decode(q[f]) * 0.0;"),
+    ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
 ]
 
 
