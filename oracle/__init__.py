@@ -46,7 +46,10 @@ class Oracle:
         L.cmo_eval_fp8.argtypes = [_f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int32, _f32p,
                                    np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"),
-                                   _f32p, _f64p, ctypes.c_int32]
+                                   _f32p, _f64p, ctypes.c_void_p, ctypes.c_int32]
+        L.cmo_fp8_codes.restype = None
+        L.cmo_fp8_codes.argtypes = [_f32p, ctypes.c_int64, ctypes.c_double,
+                                    np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
         L.cmo_select.restype = ctypes.c_int32
         L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
         self.L = L
@@ -92,18 +95,29 @@ class Oracle:
     def fp8_scale(self, amax: float) -> float:
         return float(self.L.cmo_fp8_scale(float(amax)))
 
+    def fp8_codes(self, x, in_scale):
+        """e4m3 codes of log1p(x) * in_scale (FP64), same shape as x."""
+        x = _f32(x)
+        out = np.empty(x.shape, np.uint8)
+        self.L.cmo_fp8_codes(x.ravel(), x.size, float(in_scale), out.reshape(-1))
+        return out
+
     def eval_query_fp8(self, params, in_scale, act_scale, pipe, codes, terms, *,
-                       nthreads: int = 0):
+                       nthreads: int = 0, margin: bool = False):
         """FP64 predicted runtime of the FP8 form: codes[S][N][40] uint8 are e4m3
-        codes of log1p(x) * in_scale."""
+        codes of log1p(x) * in_scale.  margin=True also returns each
+        candidate's smallest relative distance of a scaled hidden value to an
+        e4m3 rounding midpoint."""
         params, pipe, terms = _f32(params), _f32(pipe), _f32(terms)
         codes = np.ascontiguousarray(codes, dtype=np.uint8)
         S, N = codes.shape[0], codes.shape[1]
         assert codes.shape == (S, N, 40) and pipe.shape == (S, 56) and terms.shape == (S, N, 8)
         cost = np.empty(N, np.float64)
+        marg = np.empty(N, np.float64) if margin else None
         self.L.cmo_eval_fp8(params, float(in_scale), float(act_scale), S, N, pipe, codes,
-                            terms, cost, int(nthreads))
-        return cost
+                            terms, cost, None if marg is None else marg.ctypes.data_as(ctypes.c_void_p),
+                            int(nthreads))
+        return (cost, marg) if margin else cost
 
     def select(self, cost, k: int):
         """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""
@@ -143,6 +157,10 @@ def select(cost, k: int):
 
 def eval_query_fp8(*a, **kw):
     return lib().eval_query_fp8(*a, **kw)
+
+
+def fp8_codes(x, in_scale):
+    return lib().fp8_codes(x, in_scale)
 
 
 def e4m3_encode(v: float) -> int:

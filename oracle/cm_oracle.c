@@ -197,9 +197,34 @@ double cmo_fp8_scale(double amax)
 
 static double q8(double v) { return cmo_e4m3_decode(cmo_e4m3_encode(v)); }
 
+void cmo_fp8_codes(const float *x, int64_t n, double in_scale, uint8_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = cmo_e4m3_encode(log1p((double)x[i]) * in_scale);
+}
+
+/* Relative distance from x >= 0 to the nearest point where e4m3 rounding
+ * changes code: a midpoint between two neighbouring finite codes.  Above 448
+ * every value saturates, so there is no such point beyond the last midpoint. */
+static double midpoint_distance(double x)
+{
+    const uint8_t c = cmo_e4m3_encode(x);
+    const double v = cmo_e4m3_decode(c);
+    double d = INFINITY;
+    if (c > 0x00) {
+        const double lo = 0.5 * (cmo_e4m3_decode((uint8_t)(c - 1)) + v);
+        d = fabs(x - lo) / lo;
+    }
+    if (c < 0x7E) {
+        const double hi = 0.5 * (v + cmo_e4m3_decode((uint8_t)(c + 1)));
+        const double dh = fabs(hi - x) / hi;
+        if (dh < d) d = dh;
+    }
+    return d;
+}
+
 void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
                   int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
-                  double *cost_out, int32_t nthreads)
+                  double *cost_out, double *margin_out, int32_t nthreads)
 {
     cmo_params P = split_params(params);
     /* folded first layer over the schedule features and its bias share */
@@ -249,7 +274,7 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
 #pragma omp parallel for schedule(static) num_threads(nthreads)
 #endif
     for (int64_t i = 0; i < (int64_t)N; ++i) {
-        double stage_sum = 0.0;
+        double stage_sum = 0.0, margin = INFINITY;
         for (int64_t s = 0; s < (int64_t)S; ++s) {
             const int64_t row = s * (int64_t)N + i;
             const uint8_t *q = codes + row * FS;
@@ -258,7 +283,12 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
                 double a = s1 * u[s * H + h];
                 for (int f = 0; f < FS; ++f) a += Wq1[h][f] * cmo_e4m3_decode(q[f]);
                 const double pre = a / s1;
-                hq[h] = q8((pre < 0.0 ? 0.0 : pre) * act_scale); /* ReLU, then quantize */
+                const double x = (pre < 0.0 ? 0.0 : pre) * act_scale; /* ReLU, scale */
+                hq[h] = q8(x);
+                if (margin_out) {
+                    const double d = midpoint_distance(x);
+                    if (d < margin || isnan(d)) margin = d;
+                }
             }
             double v = 0.0;
             for (int c = 0; c < C; ++c) {
@@ -270,6 +300,7 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
             stage_sum += v;
         }
         cost_out[i] = stage_sum;
+        if (margin_out) margin_out[i] = margin;
     }
     free(u);
     (void)nthreads;

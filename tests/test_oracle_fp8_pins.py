@@ -139,3 +139,38 @@ def test_fp8_form_close_to_fp64_model(oracle_mod):
         got = oracle_mod.eval_query_fp8(params, in_scale, act_scale, q.pipe, codes, q.terms)
         rel = np.abs(got - ref) / ref
         assert np.median(rel) < 0.05 and rel.max() < 0.5, (act_scale, np.median(rel), rel.max())
+
+
+def test_fp8_input_codes(oracle_mod):
+    """Input codes are e4m3(log1p(x) * s_in): log1p(0) = 0, log1p(-1) = -inf
+    saturates to -448, x < -1 has no logarithm (NaN code), log1p(x) = 1.1 lies
+    between the codes 1.0 and 1.125, nearer the second, and log1p(1e30) = 69.08
+    between 64 and 72 (step 8 in [64, 128)), nearer 72; times 8 it saturates."""
+    x = np.array([0.0, -1.0, -2.0, math.expm1(1.1), math.expm1(1.1), np.inf, 1e30, np.nan],
+                 np.float32)
+    got = oracle_mod.fp8_codes(x, 1.0)
+    assert got.tolist() == [0x00, 0xFE, 0x7F, 0x39, 0x39, 0x7E, 0x69, 0x7F]
+    assert oracle_mod.fp8_codes(x[3:4], 4.0).tolist() == [0x49]   # 4.4 -> 4.5
+    assert oracle_mod.fp8_codes(x[6:7], 8.0).tolist() == [0x7E]
+    rng = np.random.default_rng(5)
+    y = np.exp(rng.uniform(-12, 12, 300)).astype(np.float32)
+    want = [oracle_mod.e4m3_encode(math.log1p(float(v)) * 8.0) for v in y]
+    assert oracle_mod.fp8_codes(y.reshape(3, 100), 8.0).ravel().tolist() == want
+
+
+def test_fp8_rounding_margin(oracle_mod):
+    """The hand example's hidden units are 3, 3 and ReLU(-4) = 0 (the rest 0).
+    3 is an e4m3 value whose neighbouring midpoints are 2.875 and 3.125, so the
+    margin is 0.125 / 3.125 = 0.04 at any power-of-two hidden scale (0 is 1 away,
+    relatively, from the first midpoint 2^-10).  With b_1[0] = 0.1 unit 0 is 3.1:
+    0.025 / 3.125 = 0.008; with b_1[0] = 0.125 it sits on the midpoint: 0."""
+    g = cc.load_golden("hand_examples.json")
+    case = g["cases"][0]
+    pipe, sched, terms = cc.hand_query(case["terms"], n_cands=2)
+    codes = _codes(oracle_mod, sched, 1.0)
+    for b10, want in ((0.0, 0.04), (0.1, 0.008), (0.125, 0.0)):
+        params = cc.set_params(cc.hand_params(), {"b_1": [[0, b10]]})
+        for act_scale in (1.0, 4.0):
+            _, m = oracle_mod.eval_query_fp8(params, 1.0, act_scale, pipe, codes, terms,
+                                             margin=True)
+            assert np.allclose(m, want, rtol=1e-6, atol=1e-9), (b10, act_scale, m)

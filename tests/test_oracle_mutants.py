@@ -71,8 +71,7 @@ MUTANTS = [
     ("fp8 input scale not undone", "const double pre = a / s1;", "const double pre = a / sw1;"),
     ("fp8 activation scale not undone", "a = a / s2 + (double)P.b2[c];",
      "a = a / (s2 / act_scale) + (double)P.b2[c];"),
-    ("fp8 hidden activations not quantized", "hq[h] = q8((pre < 0.0 ? 0.0 : pre) * act_scale);",
-     "hq[h] = (pre < 0.0 ? 0.0 : pre) * act_scale;"),
+    ("fp8 hidden activations not quantized", "hq[h] = q8(x);", "hq[h] = x;"),
     ("fp8 inputs decoded as zero", "a += Wq1[h][f] * cmo_e4m3_decode(q[f]);",
      "a += Wq1[h][f] * cmo_e4m3_decode(q[f]) * 0.0;"),
     ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
