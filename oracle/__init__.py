@@ -46,7 +46,8 @@ class Oracle:
         L.cmo_eval_fp8.argtypes = [_f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int32, _f32p,
                                    np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"),
-                                   _f32p, _f64p, ctypes.c_void_p, ctypes.c_int32]
+                                   _f32p, _f64p, ctypes.c_double, ctypes.c_void_p,
+                                   ctypes.c_int32]
         L.cmo_fp8_codes.restype = None
         L.cmo_fp8_codes.argtypes = [_f32p, ctypes.c_int64, ctypes.c_double,
                                     np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
@@ -103,21 +104,22 @@ class Oracle:
         return out
 
     def eval_query_fp8(self, params, in_scale, act_scale, pipe, codes, terms, *,
-                       nthreads: int = 0, margin: bool = False):
+                       nthreads: int = 0, acc_tol=None):
         """FP64 predicted runtime of the FP8 form: codes[S][N][40] uint8 are e4m3
-        codes of log1p(x) * in_scale.  margin=True also returns each
-        candidate's smallest relative distance of a scaled hidden value to an
-        e4m3 rounding midpoint."""
+        codes of log1p(x) * in_scale.  With acc_tol also returns each
+        candidate's error bound for product sums off by acc_tol of their
+        largest term."""
         params, pipe, terms = _f32(params), _f32(pipe), _f32(terms)
         codes = np.ascontiguousarray(codes, dtype=np.uint8)
         S, N = codes.shape[0], codes.shape[1]
         assert codes.shape == (S, N, 40) and pipe.shape == (S, 56) and terms.shape == (S, N, 8)
         cost = np.empty(N, np.float64)
-        marg = np.empty(N, np.float64) if margin else None
+        bound = np.empty(N, np.float64) if acc_tol is not None else None
         self.L.cmo_eval_fp8(params, float(in_scale), float(act_scale), S, N, pipe, codes,
-                            terms, cost, None if marg is None else marg.ctypes.data_as(ctypes.c_void_p),
+                            terms, cost, float(acc_tol or 0.0),
+                            None if bound is None else bound.ctypes.data_as(ctypes.c_void_p),
                             int(nthreads))
-        return (cost, marg) if margin else cost
+        return (cost, bound) if bound is not None else cost
 
     def select(self, cost, k: int):
         """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""

@@ -167,8 +167,9 @@ double cmo_e4m3_decode(uint8_t code)
 
 /* Nearest e4m3 value, ties to the even code (the code's last bit is the
  * mantissa's last bit), magnitudes at or above 448 saturate to 448, NaN maps
- * to the positive NaN code.  Found by comparing against every finite code. */
-uint8_t cmo_e4m3_encode(double v)
+ * to the positive NaN code.  Found by comparing against every finite code;
+ * val[c] holds the value of code c for c < 0x7F. */
+static uint8_t nearest_code(const double *val, double v)
 {
     if (isnan(v)) return 0x7F;
     const uint8_t sign = signbit(v) ? 0x80 : 0x00;
@@ -177,13 +178,25 @@ uint8_t cmo_e4m3_encode(double v)
     int best = 0;
     double bd = INFINITY;
     for (int c = 0; c <= 0x7E; ++c) {
-        const double d = fabs(cmo_e4m3_decode((uint8_t)c) - a);
+        const double d = fabs(val[c] - a);
         if (d < bd || (d == bd && (c & 1) == 0)) {
             bd = d;
             best = c;
         }
     }
     return (uint8_t)(sign | best);
+}
+
+static void code_values(double *val)
+{
+    for (int c = 0; c <= 0x7E; ++c) val[c] = cmo_e4m3_decode((uint8_t)c);
+}
+
+uint8_t cmo_e4m3_encode(double v)
+{
+    double val[0x7F];
+    code_values(val);
+    return nearest_code(val, v);
 }
 
 /* The largest power of two not above 448 / amax (1 when amax is 0). */
@@ -199,32 +212,25 @@ static double q8(double v) { return cmo_e4m3_decode(cmo_e4m3_encode(v)); }
 
 void cmo_fp8_codes(const float *x, int64_t n, double in_scale, uint8_t *out)
 {
-    for (int64_t i = 0; i < n; ++i) out[i] = cmo_e4m3_encode(log1p((double)x[i]) * in_scale);
+    double val[0x7F];
+    code_values(val);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) out[i] = nearest_code(val, log1p((double)x[i]) * in_scale);
 }
 
-/* Relative distance from x >= 0 to the nearest point where e4m3 rounding
- * changes code: a midpoint between two neighbouring finite codes.  Above 448
- * every value saturates, so there is no such point beyond the last midpoint. */
-static double midpoint_distance(double x)
+/* How far the e4m3 value of x >= 0 may move when x is only known to within
+ * +-e: rounding is monotone, so any value x' in [x - e, x + e] rounds to a
+ * value between those of x - e and x + e, and so does x itself. */
+static double rounding_swing(double x, double e)
 {
-    const uint8_t c = cmo_e4m3_encode(x);
-    const double v = cmo_e4m3_decode(c);
-    double d = INFINITY;
-    if (c > 0x00) {
-        const double lo = 0.5 * (cmo_e4m3_decode((uint8_t)(c - 1)) + v);
-        d = fabs(x - lo) / lo;
-    }
-    if (c < 0x7E) {
-        const double hi = 0.5 * (v + cmo_e4m3_decode((uint8_t)(c + 1)));
-        const double dh = fabs(hi - x) / hi;
-        if (dh < d) d = dh;
-    }
-    return d;
+    return q8(x + e) - q8(x - e < 0.0 ? 0.0 : x - e);
 }
 
 void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
                   int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
-                  double *cost_out, double *margin_out, int32_t nthreads)
+                  double *cost_out, double acc_tol, double *bound_out, int32_t nthreads)
 {
     cmo_params P = split_params(params);
     /* folded first layer over the schedule features and its bias share */
@@ -251,21 +257,36 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
     for (int c = 0; c < C; ++c)
         for (int h = 0; h < H; ++h) Wq2[c][h] = q8((double)P.W2[c * H + h] * sw2);
 
-    /* per stage: the algorithm embedding's share of the first layer */
-    double *u = (double *)malloc(sizeof(double) * (size_t)(S > 0 ? S : 1) * H);
-    if (!u) return;
+    /* per stage: the algorithm embedding's share of the first layer, and the
+     * sum of the magnitudes of its terms (for the error bound) */
+    const size_t nu = (size_t)(S > 0 ? S : 1) * H;
+    double *u = (double *)malloc(sizeof(double) * nu);
+    double *uabs = (double *)malloc(sizeof(double) * nu);
+    if (!u || !uabs) {
+        free(u);
+        free(uabs);
+        return;
+    }
     for (int s = 0; s < S; ++s) {
-        double p[FP], ep[E];
+        double p[FP], ep[E], epabs[E];
         for (int f = 0; f < FP; ++f) p[f] = log1p((double)pipe[s * FP + f]);
         for (int e = 0; e < E; ++e) {
-            double a = (double)P.bp[e];
-            for (int f = 0; f < FP; ++f) a += (double)P.Wp[e * FP + f] * p[f];
+            double a = (double)P.bp[e], m = fabs((double)P.bp[e]);
+            for (int f = 0; f < FP; ++f) {
+                a += (double)P.Wp[e * FP + f] * p[f];
+                m += fabs((double)P.Wp[e * FP + f] * p[f]);
+            }
             ep[e] = a;
+            epabs[e] = m;
         }
         for (int h = 0; h < H; ++h) {
-            double a = (double)P.b1[h];
-            for (int e = 0; e < E; ++e) a += (double)P.W1[h * 2 * E + e] * ep[e];
+            double a = (double)P.b1[h], m = fabs((double)P.b1[h]) + fabs(beta[h]);
+            for (int e = 0; e < E; ++e) {
+                a += (double)P.W1[h * 2 * E + e] * ep[e];
+                m += fabs((double)P.W1[h * 2 * E + e]) * epabs[e];
+            }
             u[s * H + h] = a + beta[h];
+            uabs[s * H + h] = m;
         }
     }
     const double s1 = sw1 * in_scale, s2 = sw2 * act_scale;
@@ -274,35 +295,50 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
 #pragma omp parallel for schedule(static) num_threads(nthreads)
 #endif
     for (int64_t i = 0; i < (int64_t)N; ++i) {
-        double stage_sum = 0.0, margin = INFINITY;
+        double stage_sum = 0.0, bound = 0.0;
         for (int64_t s = 0; s < (int64_t)S; ++s) {
             const int64_t row = s * (int64_t)N + i;
             const uint8_t *q = codes + row * FS;
-            double hq[H];
+            double hq[H], swing[H];
             for (int h = 0; h < H; ++h) {
-                double a = s1 * u[s * H + h];
-                for (int f = 0; f < FS; ++f) a += Wq1[h][f] * cmo_e4m3_decode(q[f]);
+                double a = s1 * u[s * H + h], pmax = 0.0;
+                for (int f = 0; f < FS; ++f) {
+                    const double prod = Wq1[h][f] * cmo_e4m3_decode(q[f]);
+                    a += prod;
+                    if (fabs(prod) > pmax) pmax = fabs(prod);
+                }
                 const double pre = a / s1;
                 const double x = (pre < 0.0 ? 0.0 : pre) * act_scale; /* ReLU, scale */
                 hq[h] = q8(x);
-                if (margin_out) {
-                    const double d = midpoint_distance(x);
-                    if (d < margin || isnan(d)) margin = d;
+                if (bound_out) {
+                    /* a product sum off by acc_tol of its largest term, the
+                     * hoisted row off by 1e-5 of its terms' magnitudes */
+                    const double e =
+                        (acc_tol * pmax / s1 + 1e-5 * uabs[s * H + h]) * act_scale;
+                    swing[h] = isnan(x) ? 0.0 : rounding_swing(x, e);
                 }
             }
             double v = 0.0;
             for (int c = 0; c < C; ++c) {
-                double a = 0.0;
-                for (int h = 0; h < H; ++h) a += Wq2[c][h] * hq[h];
+                double a = 0.0, pmax = 0.0, flips = 0.0;
+                for (int h = 0; h < H; ++h) {
+                    a += Wq2[c][h] * hq[h];
+                    if (fabs(Wq2[c][h] * hq[h]) > pmax) pmax = fabs(Wq2[c][h] * hq[h]);
+                    if (bound_out) flips += fabs(Wq2[c][h]) * swing[h];
+                }
                 a = a / s2 + (double)P.b2[c];
                 v += (a < 0.0 ? 0.0 : a) * (double)terms[row * C + c];
+                /* ReLU moves its output by at most its input's change */
+                if (bound_out)
+                    bound += (flips + acc_tol * pmax) / s2 * fabs((double)terms[row * C + c]);
             }
             stage_sum += v;
         }
         cost_out[i] = stage_sum;
-        if (margin_out) margin_out[i] = margin;
+        if (bound_out) bound_out[i] = bound;
     }
     free(u);
+    free(uabs);
     (void)nthreads;
 }
 

@@ -39,14 +39,15 @@ void cmo_fp8_codes(const float *x, int64_t n, double in_scale, uint8_t *out);
 /* FP8 form of cmo_eval: codes[S][N][40] are e4m3 codes of log1p(x) * in_scale;
  * weights quantized per layer (first layer folded: W_1[:, 24:] W_s), hidden
  * activations quantized as e4m3(ReLU(h) * act_scale); FP64 in between.
- * margin_out[N] (optional, may be NULL): per candidate, the smallest relative
- * distance of a scaled hidden value ReLU(h) * act_scale, over its stages and
- * hidden units, to the nearest e4m3 rounding midpoint (how close the
- * candidate's result is to a different rounding decision; NaN when a hidden
- * value is NaN). */
+ * bound_out[N] (optional, may be NULL): per candidate, how far its cost may
+ * move when every sum of e4m3 products (first layer, coefficient layer) is off
+ * by acc_tol times its largest product and every hoisted row by 1e-5 of the
+ * magnitudes of its terms: the hidden values whose rounding may then change
+ * contribute their possible e4m3 swing through |W_2|, and each coefficient
+ * its own error, times |terms|. */
 void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
                   int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
-                  double *cost_out, double *margin_out, int32_t nthreads);
+                  double *cost_out, double acc_tol, double *bound_out, int32_t nthreads);
 
 /* The k best candidates: ascending cost, ties by lower index, -0 == +0, NaN
  * last; k > N pads with (-1, +inf).  Returns 0, or <0 on bad sizes / no memory. */

@@ -158,19 +158,29 @@ def test_fp8_input_codes(oracle_mod):
     assert oracle_mod.fp8_codes(y.reshape(3, 100), 8.0).ravel().tolist() == want
 
 
-def test_fp8_rounding_margin(oracle_mod):
-    """The hand example's hidden units are 3, 3 and ReLU(-4) = 0 (the rest 0).
-    3 is an e4m3 value whose neighbouring midpoints are 2.875 and 3.125, so the
-    margin is 0.125 / 3.125 = 0.04 at any power-of-two hidden scale (0 is 1 away,
-    relatively, from the first midpoint 2^-10).  With b_1[0] = 0.1 unit 0 is 3.1:
-    0.025 / 3.125 = 0.008; with b_1[0] = 0.125 it sits on the midpoint: 0."""
+def test_fp8_error_bound(oracle_mod):
+    """Error bound of the hand examples (hidden units h = 3 + b_1[0], 3 and
+    ReLU(-4) = 0; W_2 rows (1, 0, 0), (0, 2, 1), (-1, 0, 0); terms H1: 10, 100,
+    1000 for coefficients 0..2; H2 adds a stage with 1, 2, 0).
+    Coefficient sums off by tau of their largest product: tau * (3*10 + 6*100 +
+    3*1000) = 3630 tau for H1, + tau * (3*1 + 6*2) for H2's second stage.
+    Hidden rounding: the hoisted rows are off by at most 1e-5 of their terms'
+    magnitudes (3 + b_1[0], 7, 4), far from any e4m3 midpoint when b_1[0] = 0;
+    with b_1[0] = 0.125 - 2^-20 unit 0 sits just below the midpoint 3.125 of 3
+    and 3.25, may round either way, and adds 0.25 * |W_2[:, 0]| . terms =
+    0.25 * (10 + 1000) = 252.5 per H1 stage (0.25 * 1 for H2's second)."""
     g = cc.load_golden("hand_examples.json")
-    case = g["cases"][0]
-    pipe, sched, terms = cc.hand_query(case["terms"], n_cands=2)
-    codes = _codes(oracle_mod, sched, 1.0)
-    for b10, want in ((0.0, 0.04), (0.1, 0.008), (0.125, 0.0)):
-        params = cc.set_params(cc.hand_params(), {"b_1": [[0, b10]]})
-        for act_scale in (1.0, 4.0):
-            _, m = oracle_mod.eval_query_fp8(params, 1.0, act_scale, pipe, codes, terms,
-                                             margin=True)
-            assert np.allclose(m, want, rtol=1e-6, atol=1e-9), (b10, act_scale, m)
+    want = {("H1", 0.0): (0.0, 3630.0), ("H2", 0.0): (0.0, 3645.0),
+            ("H1", 0.125 - 2.0 ** -20): (252.5, 3630.0), ("H2", 0.125 - 2.0 ** -20): (252.75, 3645.0)}
+    for case in g["cases"]:
+        pipe, sched, terms = cc.hand_query(case["terms"], n_cands=2)
+        codes = _codes(oracle_mod, sched, 1.0)
+        for b10 in (0.0, 0.125 - 2.0 ** -20):
+            params = cc.set_params(cc.hand_params(), {"b_1": [[0, b10]]})
+            flips, per_tau = want[(case["name"], b10)]
+            for act_scale in (1.0, 4.0):
+                for tau in (0.0, 2e-3):
+                    _, bd = oracle_mod.eval_query_fp8(params, 1.0, act_scale, pipe, codes, terms,
+                                                      acc_tol=tau)
+                    assert np.allclose(bd, flips + per_tau * tau, rtol=1e-9, atol=1e-12), \
+                        (case["name"], b10, act_scale, tau, bd)

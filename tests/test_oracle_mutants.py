@@ -39,6 +39,8 @@ PIN_TESTS = [
     fp8pins.test_fp8_form_quantizes_hidden_and_inputs,
     fp8pins.test_fp8_form_invariants,
     fp8pins.test_fp8_form_close_to_fp64_model,
+    fp8pins.test_fp8_input_codes,
+    fp8pins.test_fp8_error_bound,
 ]
 
 # (name, text in cm_oracle.c, replacement)
@@ -72,8 +74,14 @@ MUTANTS = [
     ("fp8 activation scale not undone", "a = a / s2 + (double)P.b2[c];",
      "a = a / (s2 / act_scale) + (double)P.b2[c];"),
     ("fp8 hidden activations not quantized", "hq[h] = q8(x);", "hq[h] = x;"),
-    ("fp8 inputs decoded as zero", "a += Wq1[h][f] * cmo_e4m3_decode(q[f]);",
-     "a += Wq1[h][f] * cmo_e4m3_decode(q[f]) * 0.0;"),
+    ("fp8 inputs decoded as zero", "const double prod = Wq1[h][f] * cmo_e4m3_decode(q[f]);",
+     "const double prod = Wq1[h][f] * cmo_e4m3_decode(q[f]) * 0.0;"),
+    ("fp8 bound ignores rounding swings", "flips += fabs(Wq2[c][h]) * swing[h];",
+     "flips += 0.0 * swing[h];"),
+    ("fp8 bound ignores coefficient sums", "bound += (flips + acc_tol * pmax) / s2",
+     "bound += (flips + 0.0 * pmax) / s2"),
+    ("fp8 bound ignores the hoisted row", "+ 1e-5 * uabs[s * H + h]) * act_scale;",
+     "+ 0.0 * uabs[s * H + h]) * act_scale;"),
     ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
 ]
 
