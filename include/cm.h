@@ -72,9 +72,16 @@ enum {
  *            the two dense layers run on bf16 matrix cores with float32
  *            accumulation, each product split into high and low bf16 parts
  *            (three bf16 products) so that the arithmetic error stays near
- *            float32; cost terms stay float32. */
+ *            float32; cost terms stay float32.
+ *   CM_FP8:  schedule features stored as OCP e4m3 codes of
+ *            log1p(x) * s_in (1 byte each; cm_fp8_encode writes them), so the
+ *            log transform is done once at encoding; both dense layers run on
+ *            fp8 matrix cores with e4m3 weights, the hidden activations are
+ *            re-quantized to e4m3, accumulation and cost terms are float32.
+ *            The model must first be given its FP8 form with
+ *            cm_model_prepare_fp8 (the scales s_in and s_h). */
 typedef int32_t cm_precision;
-enum { CM_FP32 = 0, CM_BF16 = 1 };
+enum { CM_FP32 = 0, CM_BF16 = 1, CM_FP8 = 2 };
 
 typedef void *cm_stream; /* hipStream_t */
 
@@ -127,7 +134,8 @@ cm_status cm_workspace_destroy(cm_workspace *ws);
  * the batch's base pointers:
  *   pipe  + pipe_off  : float32 [n_stages][56]          algorithm features
  *   sched + sched_off : [n_stages][n_cands][40]         schedule features,
- *                       float32 (CM_FP32) or bfloat16 bits (CM_BF16);
+ *                       float32 (CM_FP32), bfloat16 bits (CM_BF16) or
+ *                       e4m3 codes (CM_FP8, see cm_fp8_encode);
  *                       sched_off must be a multiple of 8 elements
  *   terms + terms_off : float32 [n_stages][n_cands][8]  cost terms;
  *                       terms_off must be a multiple of 4
@@ -164,9 +172,10 @@ typedef struct {
  * any batch.
  * cost_out is a device pointer; results land at cost_out[cost_off + i].
  * Asynchronous on `stream`; allocates nothing.
- * Errors: CM_EINVAL (bad descriptor, misaligned offset, NULL pointer),
- * CM_E2BIG (batch exceeds the workspace), CM_EUNSUPPORTED (precision),
- * CM_EDEVICE (launch failure). */
+ * CM_FP8 evaluates the FP8 form described below (cm_model_prepare_fp8).
+ * Errors: CM_EINVAL (bad descriptor, misaligned offset, NULL pointer, CM_FP8
+ * on a model without an FP8 form), CM_E2BIG (batch exceeds the workspace),
+ * CM_EUNSUPPORTED (precision), CM_EDEVICE (launch failure). */
 cm_status cm_eval_batch(const cm_model *model, cm_precision precision,
                         const cm_batch *batch, cm_workspace *ws, float *cost_out,
                         cm_stream stream);
@@ -175,8 +184,10 @@ cm_status cm_eval_batch(const cm_model *model, cm_precision precision,
  * every candidate of its query, so their share of the first layer is
  * computed once per stage:
  *   U[row][j] = b_1[j] + sum_e W_1[j][e] (W_p log1p(pipe[s]) + b_p)[e]
- * (for CM_BF16 also + sum_e W_1[j][24 + e] b_s[e], since that form folds the
- * schedule embedding into the first layer).  Rows are written in batch order:
+ * (for CM_BF16 and CM_FP8 also + sum_e W_1[j][24 + e] b_s[e], since those
+ * forms fold the schedule embedding into the first layer; for CM_FP8 the row
+ * is then multiplied by s_h, that form's hidden scale, as set by the model's
+ * last cm_model_prepare_fp8).  Rows are written in batch order:
  * query q's stage s goes to row (n_stages of queries 0..q-1) + s, 32 floats
  * per row, into U_out (device, 16-byte aligned, at least sum(n_stages) * 32
  * floats).  Only n_stages, pipe_off and pipe are read.  Asynchronous on
@@ -205,6 +216,59 @@ cm_status cm_eval_hoisted(const cm_model *model, cm_precision precision,
 cm_status cm_topk_per_query(const float *cost, const cm_batch *batch, int32_t k,
                             cm_workspace *ws, int32_t *idx_out, float *val_out,
                             cm_stream stream);
+
+/* ------------------------------------------------------------------------
+ * FP8 form (CM_FP8).  An 8-bit reading of the model of Sec. 5.2: every
+ * quantization point is an OCP e4m3 value (sign, 4 exponent bits with bias
+ * 7, 3 mantissa bits, subnormals, largest finite 448, no infinities, NaN
+ * codes 0x7F and 0xFF), rounded to nearest with ties to the even code and
+ * saturated at +-448; each scale is a power of two, so scaling and unscaling
+ * are exact.  Per stage s and candidate i:
+ *   code[f] = e4m3(log1p(sched[s][i][f]) * s_in)                (input)
+ *   a[j]    = sum_f e4m3(Wf[j][f] s_w1) dec(code[f])            (fp8 matrix core)
+ *   h[j]    = e4m3(ReLU(a[j] / (s_w1 s_in) + U[s][j]) * s_h)    (hidden)
+ *   c[m]    = ReLU(sum_j e4m3(W_2[m][j] s_w2) h[j] / (s_w2 s_h) + b_2[m])
+ *   cost[i] = sum_s sum_m c[m] terms[s][i][m]   (Kahan float32, stage parts
+ *                                                 as for CM_BF16)
+ * with Wf = W_1[:, 24:] W_s (the schedule embedding folded into the first
+ * layer), U[s] the hoisted row of cm_hoist_stages before its FP8 scale, and
+ * s_w1, s_w2 the largest powers of two with s |W| <= 448 over Wf and W_2.
+ * The matrix instruction sums its e4m3 products with less than float32
+ * precision (measured on gfx950: within about 6e-4 of the largest product),
+ * so a hidden value that lands that close to an e4m3 rounding midpoint may
+ * round to the neighbouring code; the hoisted row is added afterwards in
+ * float32.  A NaN code gives a NaN cost.
+ * ------------------------------------------------------------------------ */
+
+/* Derive the FP8 form of `model` for input scale s_in = in_scale and hidden
+ * scale s_h = act_scale (both positive powers of two; every derived scale
+ * must stay within [2^-60, 2^60]).  Host work plus one small synchronous
+ * copy to the model's device.  Replaces an earlier FP8 form; must not run
+ * while any call that uses this model with CM_FP8 is in flight, and rows
+ * hoisted for CM_FP8 before it are stale after it.
+ * Errors: CM_EINVAL (NULL model, scale not a power of two or out of range),
+ * CM_ENOMEM, CM_EDEVICE. */
+cm_status cm_model_prepare_fp8(cm_model *model, float in_scale, float act_scale);
+
+/* Suggested scales for the FP8 form from a host sample of n_rows (stage,
+ * candidate) rows: pipe_rows[n_rows][56] and sched_rows[n_rows][40], raw
+ * float32 features as for CM_FP32.  *in_scale_out is the largest power of
+ * two s with s * 2 * max|log1p(x)| <= 448 over the schedule features;
+ * *act_scale_out the same over the float64 model's hidden activations
+ * ReLU(h) (a factor 2 of headroom for rows outside the sample; 1 when the
+ * maximum is 0).  Rows with a non-finite value are skipped.  Host only.
+ * Errors: CM_EINVAL (NULL pointer, n_rows < 1). */
+cm_status cm_fp8_calibrate(const cm_model *model, int64_t n_rows, const float *pipe_rows,
+                           const float *sched_rows, float *in_scale_out,
+                           float *act_scale_out);
+
+/* codes[i] = e4m3(log1pf(x[i]) * in_scale) for i < n, on the device: x is
+ * float32 (device, 16-byte aligned), codes uint8 (device, 16-byte aligned,
+ * may not overlap x).  Round to nearest even, saturation at +-448, NaN (e.g.
+ * x < -1) -> 0x7F.  in_scale: a positive power of two.  Asynchronous on
+ * `stream`; allocates nothing.  Errors: CM_EINVAL, CM_EDEVICE. */
+cm_status cm_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t *codes,
+                        cm_stream stream);
 
 /* ------------------------------------------------------------------------
  * Persistent beam step: hoist + evaluate + select for a ragged batch in one

@@ -12,19 +12,19 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (CM_BF16, CM_FP32, CM_MAX_K, CM_N_PARAMS, CM_STAGE_CHUNK,  # noqa: F401
+from ._lib import (CM_BF16, CM_FP8, CM_FP32, CM_MAX_K, CM_N_PARAMS, CM_STAGE_CHUNK,  # noqa: F401
                    CmError, check, lib)
 
 __all__ = [
-    "CM_FP32", "CM_BF16", "CM_MAX_K", "CmError", "Model", "Workspace", "Batch",
+    "CM_FP32", "CM_BF16", "CM_FP8", "CM_MAX_K", "CmError", "Model", "Workspace", "Batch",
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
     "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
     "cm_version", "pack_queries", "Step", "cm_step_create", "cm_step_destroy", "cm_step_run",
     "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
-    "Server", "cm_server_create",
+    "Server", "cm_server_create", "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
 ]
 
-PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16}
+PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16, "fp8": CM_FP8}
 
 lib()  # fail at import when the HIP library is missing
 
@@ -120,6 +120,39 @@ def cm_model_create(params) -> Model:
 
 def cm_model_destroy(model: Model):
     model.close()
+
+
+def cm_model_prepare_fp8(model: Model, in_scale: float, act_scale: float):
+    """Derive the model's FP8 (e4m3) form for input scale in_scale and hidden
+    scale act_scale (powers of two)."""
+    check(lib().cm_model_prepare_fp8(model.handle, float(in_scale), float(act_scale)))
+
+
+def cm_fp8_calibrate(model: Model, pipe_rows, sched_rows):
+    """(in_scale, act_scale) suggested for the FP8 form from host rows
+    pipe_rows[n][56], sched_rows[n][40] (raw float32 features)."""
+    p = np.ascontiguousarray(pipe_rows, np.float32).reshape(-1, 56)
+    x = np.ascontiguousarray(sched_rows, np.float32).reshape(-1, 40)
+    if p.shape[0] != x.shape[0]:
+        raise ValueError("pipe_rows and sched_rows differ in row count")
+    a, b = ctypes.c_float(), ctypes.c_float()
+    check(lib().cm_fp8_calibrate(model.handle, int(p.shape[0]), p.ctypes.data_as(ctypes.c_void_p),
+                                 x.ctypes.data_as(ctypes.c_void_p), ctypes.byref(a),
+                                 ctypes.byref(b)))
+    return a.value, b.value
+
+
+def cm_fp8_encode(x, in_scale: float, codes_out=None, stream=None):
+    """e4m3 codes of log1p(x) * in_scale (x: float32 device tensor) into
+    codes_out (uint8 device tensor of x.numel() values, allocated if None)."""
+    import torch
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 tensor")
+    if codes_out is None:
+        codes_out = torch.empty(x.numel(), dtype=torch.uint8, device=x.device)
+    check(lib().cm_fp8_encode(_ptr(x), int(x.numel()), float(in_scale), _ptr(codes_out),
+                              _stream_handle(stream)))
+    return codes_out
 
 
 def cm_workspace_create(max_queries, max_stages, max_cands, max_rows, max_k=32) -> Workspace:
@@ -348,12 +381,13 @@ def cm_server_create(model: Model, k=32, arena_bytes=8 << 30, max_slots=2, max_p
     return Server(h, model, int(k))
 
 
-def pack_queries(queries, precision, device="cuda"):
+def pack_queries(queries, precision, device="cuda", in_scale=None):
     """Lay a list of queries (objects with pipe[S][56], sched[S][N][40],
     terms[S][N][8] float32 arrays) out in the ABI's flat device arrays.
 
-    The schedule features are stored as float32 (fp32) or as bfloat16
-    (bf16, round to nearest even).  Returns (Batch, cost tensor).
+    The schedule features are stored as float32 (fp32), as bfloat16 (bf16,
+    round to nearest even) or as e4m3 codes written by cm_fp8_encode with
+    in_scale (fp8).  Returns (Batch, cost tensor).
     """
     import torch
     prec = PRECISIONS.get(precision, precision)
@@ -371,7 +405,12 @@ def pack_queries(queries, precision, device="cuda"):
         co += N
     pipe_t = torch.from_numpy(np.concatenate(pipes) if pipes else np.zeros(1, np.float32)).to(device)
     sched_f = torch.from_numpy(np.concatenate(scheds) if scheds else np.zeros(8, np.float32)).to(device)
-    sched_t = sched_f if prec == CM_FP32 else sched_f.to(torch.bfloat16)
+    if prec == CM_FP8:
+        if in_scale is None:
+            raise ValueError("fp8 needs in_scale")
+        sched_t = cm_fp8_encode(sched_f, in_scale)
+    else:
+        sched_t = sched_f if prec == CM_FP32 else sched_f.to(torch.bfloat16)
     terms_t = torch.from_numpy(np.concatenate(terms) if terms else np.zeros(4, np.float32)).to(device)
     cost_t = torch.zeros(max(co, 1), dtype=torch.float32, device=device)
     return Batch(descs, pipe_t, sched_t, terms_t), cost_t

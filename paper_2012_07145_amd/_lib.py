@@ -16,7 +16,7 @@ CM_ENOTFOUND, CM_ECANCELED, CM_EUNSUPPORTED = -6, -7, -8
 STATUS_NAMES = {0: "CM_OK", -1: "CM_EINVAL", -2: "CM_ENOMEM", -3: "CM_EDEVICE",
                 -4: "CM_EAGAIN", -5: "CM_E2BIG", -6: "CM_ENOTFOUND", -7: "CM_ECANCELED",
                 -8: "CM_EUNSUPPORTED"}
-CM_FP32, CM_BF16 = 0, 1
+CM_FP32, CM_BF16, CM_FP8 = 0, 1, 2
 CM_MAX_K = 256
 CM_N_PARAMS = 4184
 CM_STAGE_CHUNK = 16
@@ -32,6 +32,7 @@ EXPORTS = (
     "cm_session_beam", "cm_serve_submit", "cm_serve_poll", "cm_serve_wait",
     "cm_serve_submit_batch", "cm_serve_wait_all",
     "cm_server_get_stats", "cm_server_reset_stats",
+    "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_last_error", "cm_version",
 )
 
@@ -150,6 +151,10 @@ def lib():
         L.cm_serve_wait_all.argtypes = [vp, i32, vp, i32, ctypes.POINTER(cm_result)]
         L.cm_server_get_stats.argtypes = [vp, ctypes.POINTER(cm_server_stats)]
         L.cm_server_reset_stats.argtypes = [vp]
+        fl = ctypes.c_float
+        L.cm_model_prepare_fp8.argtypes = [vp, fl, fl]
+        L.cm_fp8_calibrate.argtypes = [vp, i64, vp, vp, ctypes.POINTER(fl), ctypes.POINTER(fl)]
+        L.cm_fp8_encode.argtypes = [vp, i64, fl, vp, vp]
         for f in ("cm_model_create", "cm_model_destroy", "cm_workspace_create",
                   "cm_workspace_destroy", "cm_eval_batch", "cm_hoist_stages",
                   "cm_eval_hoisted", "cm_topk_per_query", "cm_step_create",
@@ -158,14 +163,14 @@ def lib():
                   "cm_server_create", "cm_server_destroy", "cm_session_open",
                   "cm_session_close", "cm_session_beam", "cm_serve_submit", "cm_serve_poll",
                   "cm_serve_wait", "cm_server_get_stats", "cm_server_reset_stats",
-                  "cm_serve_submit_batch", "cm_serve_wait_all"):
+                  "cm_serve_submit_batch", "cm_serve_wait_all", "cm_model_prepare_fp8",
+                  "cm_fp8_calibrate", "cm_fp8_encode"):
             getattr(L, f).restype = i32
         L.cm_last_error.restype = ctypes.c_char_p
         L.cm_last_error.argtypes = []
         L.cm_version.restype = i32
         L.cm_version.argtypes = []
         _L = L
-        del i64
     return _L
 
 

@@ -64,6 +64,43 @@ void split_bf16(double w, uint16_t &hi, uint16_t &lo)
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// OCP e4m3 code of v: round to nearest with ties to the even code, saturate
+// at +-448, NaN -> 0x7F.  The quantum of |v| is 2^(floor(log2 |v|) - 3) in the
+// normal range and 2^-9 below 2^-6; the rounded multiple n of the quantum
+// gives the code directly (n <= 8 below 2^-6: the code is n; above: the
+// exponent field is the binade + 7 and the mantissa field n - 8).
+uint8_t e4m3_code(double v)
+{
+    if (std::isnan(v)) return 0x7F;
+    const uint8_t sign = std::signbit(v) ? 0x80 : 0x00;
+    double a = std::fabs(v);
+    if (a >= 448.0) return sign | 0x7E;
+    const int binade = a >= 0x1p-6 ? std::ilogb(a) : -6;
+    const double quantum = std::ldexp(1.0, binade - 3);
+    const double n = std::nearbyint(a / quantum);  // default rounding: to even
+    a = std::min(n * quantum, 448.0);
+    if (a < 0x1p-6) return sign | (uint8_t)(a * 512.0);
+    const int e = std::ilogb(a);
+    const int mant = (int)(std::ldexp(a, -e) * 8.0) - 8;
+    return sign | (uint8_t)(((e + 7) << 3) | mant);
+}
+
+// Largest power of two p with p * amax <= 448 (1 when amax is 0).
+double pow2_scale(double amax)
+{
+    if (!(amax > 0.0)) return 1.0;
+    return std::ldexp(1.0, std::ilogb(448.0 / amax));
+}
+
+bool is_pow2(float v)
+{
+    if (!(v > 0.f) || !std::isfinite(v)) return false;
+    int e;
+    return std::frexp(v, &e) == 0.5f;
+}
+
+bool scale_in_range(double v) { return v >= 0x1p-60 && v <= 0x1p60; }
+
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <class T>
@@ -85,6 +122,8 @@ void free_model(cm::Model &m)
     if (m.d_params) (void)hipFree(m.d_params);
     if (m.d_beta) (void)hipFree(m.d_beta);
     if (m.d_bf16) (void)hipFree(m.d_bf16);
+    if (m.d_fp8) (void)hipFree(m.d_fp8);
+    delete[] m.h_params;
     m = cm::Model{};
 }
 
@@ -223,6 +262,12 @@ cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model 
         }
     for (int mo = 0; mo < C; ++mo) pk.b2[mo] = params[OFF_B2 + mo];
 
+    m.h_params = new (std::nothrow) float[N_PARAMS];
+    if (!m.h_params) {
+        delete M;
+        return fail(CM_ENOMEM, "host allocation failed");
+    }
+    std::memcpy(m.h_params, params, N_PARAMS * sizeof(float));
     cm_status st;
     if ((st = dev_alloc(&m.d_params, N_PARAMS, "parameters")) != CM_OK ||
         (st = dev_alloc(&m.d_beta, H, "beta")) != CM_OK ||
@@ -382,7 +427,8 @@ cm_status hoist_impl(const cm_model *M, cm_precision prec, const cm_batch *b, fl
         const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
         EvalLaunch L;
         fill_eval_launch(L, b, g0, ng, stage_prefix, prec);
-        CM_HIP(launch_hoist(L, M->m, prec != CM_FP32, b->pipe, U, s));
+        CM_HIP(launch_hoist(L, M->m, prec != CM_FP32, prec == CM_FP8 ? M->m.fp8_uscale : 1.f,
+                            b->pipe, U, s));
         stage_prefix += L.nstages;
     }
     return CM_OK;
@@ -399,6 +445,9 @@ cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, con
         fill_eval_launch(L, b, g0, ng, stage_prefix, prec);
         if (prec == CM_FP32)
             CM_HIP(launch_eval_fp32(L, M->m, (const float *)b->sched, b->terms, U, cost_out, s));
+        else if (prec == CM_FP8)
+            CM_HIP(launch_eval_fp8(L, M->m, (const uint8_t *)b->sched, b->terms, U, cost_out,
+                                   s));
         else
             CM_HIP(launch_eval_bf16(L, M->m, (const uint16_t *)b->sched, b->terms, U, cost_out,
                                     s));
@@ -411,8 +460,10 @@ cm_status check_eval(const cm_model *M, cm_precision prec, const cm_batch *b,
                      const cm_workspace *W, const float *cost_out, int64_t *cands)
 {
     if (!M || !W) return fail(CM_EINVAL, "model or workspace is NULL");
-    if (prec != CM_FP32 && prec != CM_BF16)
+    if (prec != CM_FP32 && prec != CM_BF16 && prec != CM_FP8)
         return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
+    if (prec == CM_FP8 && !M->m.d_fp8)
+        return fail(CM_EINVAL, "model has no FP8 form (cm_model_prepare_fp8)");
     cm_status st = check_batch(b, W->w, prec, true);
     if (st != CM_OK) return st;
     if ((st = check_device(M->m.device)) != CM_OK) return st;
@@ -431,8 +482,10 @@ cm_status cm_hoist_stages(const cm_model *M, cm_precision prec, const cm_batch *
                           cm_stream stream)
 {
     if (!M) return fail(CM_EINVAL, "model is NULL");
-    if (prec != CM_FP32 && prec != CM_BF16)
+    if (prec != CM_FP32 && prec != CM_BF16 && prec != CM_FP8)
         return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
+    if (prec == CM_FP8 && !M->m.d_fp8)
+        return fail(CM_EINVAL, "model has no FP8 form (cm_model_prepare_fp8)");
     cm_status st = check_queries(b);
     if (st != CM_OK) return st;
     if (b->n_queries == 0) return CM_OK;
@@ -504,6 +557,124 @@ cm_status cm_topk_per_query(const float *cost, const cm_batch *b, int32_t k, cm_
         L.ntasks = (int32_t)tile;
         CM_HIP(launch_topk(L, cost, w.d_tpart, w.d_tcnt, idx_out, val_out, s));
     }
+    return CM_OK;
+}
+
+// ------------------------------------------------------------------ FP8 form
+
+cm_status cm_model_prepare_fp8(cm_model *M, float in_scale, float act_scale)
+{
+    using namespace cm;
+    if (!M) return fail(CM_EINVAL, "model is NULL");
+    if (!is_pow2(in_scale) || !is_pow2(act_scale))
+        return fail(CM_EINVAL, "in_scale and act_scale must be positive powers of two");
+    cm_status st = check_device(M->m.device);
+    if (st != CM_OK) return st;
+    const float *p = M->m.h_params;
+    const float *Ws = p + OFF_WS, *W1 = p + OFF_W1, *W2 = p + OFF_W2;
+
+    // folded first layer over the schedule features: Wf = W_1[:, 24:] W_s
+    static_assert(sizeof(Fp8Pack) % 16 == 0, "Fp8Pack size");
+    double Wf[H][FS];
+    double amax1 = 0.0, amax2 = 0.0;
+    for (int j = 0; j < H; ++j)
+        for (int f = 0; f < FS; ++f) {
+            double a = 0.0;
+            for (int e = 0; e < E; ++e) a += (double)W1[j * 2 * E + E + e] * (double)Ws[e * FS + f];
+            Wf[j][f] = a;
+            amax1 = std::max(amax1, std::fabs(a));
+        }
+    for (int i = 0; i < C * H; ++i) amax2 = std::max(amax2, std::fabs((double)W2[i]));
+    const double sw1 = pow2_scale(amax1), sw2 = pow2_scale(amax2);
+    const double su = sw1 * in_scale, r1 = act_scale / su, r2 = 1.0 / (sw2 * act_scale);
+    if (!scale_in_range(su) || !scale_in_range(r1) || !scale_in_range(r2))
+        return fail(CM_EINVAL, "FP8 scales out of range (s_w1 %g, s_w2 %g, s_in %g, s_h %g)", sw1,
+                    sw2, (double)in_scale, (double)act_scale);
+
+    Fp8Pack pk;
+    std::memset(&pk, 0, sizeof pk);
+    for (int lane = 0; lane < 64; ++lane) {
+        const int m = lane & 31, h = lane >> 5;
+        uint8_t a1[32] = {}, a2[32] = {};
+        // first layer: byte j of lane m + 32h meets schedule feature 20h + j
+        for (int j = 0; j < 20; ++j) a1[j] = e4m3_code(Wf[m][20 * h + j] * sw1);
+        // coefficient layer: byte j of lane m + 32h meets hidden unit
+        // (j / 4) * 8 + 4h + j % 4, the unit the first layer's accumulator
+        // register j holds in that lane half
+        if (m < C)
+            for (int j = 0; j < 16; ++j)
+                a2[j] = e4m3_code((double)W2[m * H + (j / 4) * 8 + 4 * h + j % 4] * sw2);
+        std::memcpy(pk.a1[lane], a1, 32);
+        std::memcpy(pk.a2[lane], a2, 32);
+    }
+    for (int c = 0; c < C; ++c) pk.b2[c] = p[OFF_B2 + c];
+    pk.r1 = (float)r1;
+    pk.r2 = (float)r2;
+    pk.uh = act_scale;
+
+    Fp8Pack *d = M->m.d_fp8;
+    if (!d && (st = dev_alloc(&d, 1, "fp8 operands")) != CM_OK) return st;
+    if (hipMemcpy(d, &pk, sizeof pk, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        if (!M->m.d_fp8) (void)hipFree(d);
+        return fail(CM_EDEVICE, "copy of the FP8 operands failed");
+    }
+    M->m.d_fp8 = d;
+    M->m.fp8_uscale = act_scale;
+    return CM_OK;
+}
+
+cm_status cm_fp8_calibrate(const cm_model *M, int64_t n_rows, const float *pipe_rows,
+                           const float *sched_rows, float *in_scale_out, float *act_scale_out)
+{
+    using namespace cm;
+    if (!M || !pipe_rows || !sched_rows || !in_scale_out || !act_scale_out)
+        return fail(CM_EINVAL, "NULL argument");
+    if (n_rows < 1) return fail(CM_EINVAL, "n_rows %lld < 1", (long long)n_rows);
+    const float *p = M->m.h_params;
+    const float *Wp = p + OFF_WP, *bp = p + OFF_BP, *Ws = p + OFF_WS, *bs = p + OFF_BS;
+    const float *W1 = p + OFF_W1, *b1 = p + OFF_B1;
+    double xmax = 0.0, hmax = 0.0;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const float *pr = pipe_rows + r * FP, *sr = sched_rows + r * FS;
+        double lp[FP], ls[FS], emb[2 * E];
+        bool ok = true;
+        for (int f = 0; f < FP && ok; ++f) ok = std::isfinite(lp[f] = std::log1p((double)pr[f]));
+        for (int f = 0; f < FS && ok; ++f) ok = std::isfinite(ls[f] = std::log1p((double)sr[f]));
+        if (!ok) continue;
+        for (int f = 0; f < FS; ++f) xmax = std::max(xmax, std::fabs(ls[f]));
+        for (int e = 0; e < E; ++e) {
+            double a = bp[e], b = bs[e];
+            for (int f = 0; f < FP; ++f) a += (double)Wp[e * FP + f] * lp[f];
+            for (int f = 0; f < FS; ++f) b += (double)Ws[e * FS + f] * ls[f];
+            emb[e] = a;
+            emb[E + e] = b;
+        }
+        for (int j = 0; j < H; ++j) {
+            double a = b1[j];
+            for (int e = 0; e < 2 * E; ++e) a += (double)W1[j * 2 * E + e] * emb[e];
+            hmax = std::max(hmax, a);
+        }
+    }
+    *in_scale_out = (float)pow2_scale(2.0 * xmax);
+    *act_scale_out = (float)pow2_scale(2.0 * hmax);
+    return CM_OK;
+}
+
+cm_status cm_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t *codes,
+                        cm_stream stream)
+{
+    using namespace cm;
+    if (n < 0) return fail(CM_EINVAL, "n %lld < 0", (long long)n);
+    if (!is_pow2(in_scale)) return fail(CM_EINVAL, "in_scale must be a positive power of two");
+    if (n == 0) return CM_OK;
+    if (!x || !codes) return fail(CM_EINVAL, "x or codes is NULL");
+    if (!aligned(x, 16) || !aligned(codes, 16))
+        return fail(CM_EINVAL, "x and codes must be 16-byte aligned");
+    const uintptr_t xa = (uintptr_t)x, xb = xa + (uintptr_t)n * 4;
+    const uintptr_t ca = (uintptr_t)codes, cb = ca + (uintptr_t)n;
+    if (xa < cb && ca < xb) return fail(CM_EINVAL, "x and codes overlap");
+    CM_HIP(launch_fp8_encode(x, n, in_scale, codes, (hipStream_t)stream));
     return CM_OK;
 }
 

@@ -50,11 +50,26 @@ struct Bf16Pack {
     float b2[8];
 };
 
+// e4m3 operands of the FP8 form, laid out as the 32x32x64 fp8 matrix core
+// reads them (32 bytes per lane and operand), and its scales.
+struct Fp8Pack {
+    uint32_t a1[64][8];  // first layer: lane m + 32h, byte j < 20 = e4m3(Wf[m][20h + j] s_w1)
+    uint32_t a2[64][8];  // coefficient layer: byte j < 16 = e4m3(W_2[m][unit(h, j)] s_w2)
+    float b2[8];
+    float r1;            // s_h / (s_w1 s_in): first-layer accumulator -> scaled hidden
+    float r2;            // 1 / (s_w2 s_h): second-layer accumulator -> coefficient
+    float uh;            // s_h: scale of the hoisted rows
+    float pad;
+};
+
 struct Model {
     int device = 0;
     float *d_params = nullptr;   // float32 blob as given
     float *d_beta = nullptr;     // W_1[:, 24:] b_s (32), added when folding
     Bf16Pack *d_bf16 = nullptr;  // packed operands of the bf16 evaluator
+    Fp8Pack *d_fp8 = nullptr;    // operands of the FP8 form (after cm_model_prepare_fp8)
+    float fp8_uscale = 0.f;      // Fp8Pack::uh, kept on the host for the hoist
+    float *h_params = nullptr;   // host copy of the blob (FP8 preparation, calibration)
 };
 
 struct Workspace {
@@ -178,8 +193,12 @@ cm_status step_kernel_us(cm_step *S, float *us);
 const uint64_t *step_clock(const cm_step *S);
 
 // Kernel launchers (one per translation unit).
-hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, const float *pipe,
-                        float *U, hipStream_t st);
+hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, float scale,
+                        const float *pipe, float *U, hipStream_t st);
+hipError_t launch_eval_fp8(const EvalLaunch &L, const Model &m, const uint8_t *codes,
+                           const float *terms, const float *U, float *cost, hipStream_t st);
+hipError_t launch_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t *codes,
+                             hipStream_t st);
 hipError_t launch_eval_fp32(const EvalLaunch &L, const Model &m, const float *sched,
                             const float *terms, const float *U, float *cost, hipStream_t st);
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,

@@ -5,7 +5,7 @@
 // the first layer are computed once per stage:
 //   U[s] = W_1[:, :24] (W_p log1p(pipe[s]) + b_p) + b_1        (Sec. 5.2)
 // plus W_1[:, 24:] b_s when the evaluator folds the schedule embedding into
-// the first layer.
+// the first layer, times the hidden scale s_h of the FP8 form (1 else).
 //
 // Float32 evaluator: one thread per candidate walks the stages in ascending
 // order, computing log1p of the 40 schedule features, the schedule embedding,
@@ -31,7 +31,8 @@ __device__ inline int find_query(const EvalLaunch &L, int t, bool by_stage)
 // One stage row of the hoist by a 64-thread workgroup: p = the stage's 56
 // algorithm features, u = its 32 output floats.
 __device__ inline void hoist_row(const float *__restrict__ params, const float *__restrict__ beta,
-                                 int fold, const float *p, float *u, float *lp, float *ep)
+                                 int fold, float scale, const float *p, float *u, float *lp,
+                                 float *ep)
 {
     const int t = threadIdx.x;
     if (t < FP) lp[t] = log1pf(p[t]);
@@ -48,21 +49,21 @@ __device__ inline void hoist_row(const float *__restrict__ params, const float *
         float a = params[OFF_B1 + t];
         for (int e = 0; e < E; ++e) a = fmaf(w[e], ep[e], a);
         if (fold) a += beta[t];
-        u[t] = a;
+        u[t] = a * scale;
     }
     __syncthreads();  // lp and ep are reused by the next row
 }
 
 __global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restrict__ params,
                                               const float *__restrict__ beta, int fold,
-                                              const float *__restrict__ pipe,
+                                              float scale, const float *__restrict__ pipe,
                                               float *__restrict__ U)
 {
     __shared__ float lp[FP];
     __shared__ float ep[E];
     const int q = find_query(L, blockIdx.x, true);
     const int s = blockIdx.x - L.q[q].hrow0;
-    hoist_row(params, beta, fold, pipe + L.q[q].pipe_off + (int64_t)s * FP,
+    hoist_row(params, beta, fold, scale, pipe + L.q[q].pipe_off + (int64_t)s * FP,
               U + L.q[q].u_off + (int64_t)s * H, lp, ep);
 }
 
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(64) void k_hoist_step(const StepHead *__restrict__ 
         }
         const StepQ &D = qs[lo];
         const int s = r - row0[lo];
-        hoist_row(params, beta, 1, D.pipe + (int64_t)s * FP, D.u + (int64_t)s * H, lp, ep);
+        hoist_row(params, beta, 1, 1.f, D.pipe + (int64_t)s * FP, D.u + (int64_t)s * H, lp, ep);
     }
 }
 
@@ -161,12 +162,12 @@ __global__ __launch_bounds__(64) void k_eval_fp32(EvalLaunch L, const float *__r
 
 }  // namespace
 
-hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, const float *pipe,
-                        float *U, hipStream_t st)
+hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, float scale,
+                        const float *pipe, float *U, hipStream_t st)
 {
     if (L.nstages == 0) return hipSuccess;
     hipLaunchKernelGGL(k_hoist, dim3(L.nstages), dim3(64), 0, st, L, m.d_params, m.d_beta,
-                       fold ? 1 : 0, pipe, U);
+                       fold ? 1 : 0, scale, pipe, U);
     return hipGetLastError();
 }
 

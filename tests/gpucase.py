@@ -78,3 +78,60 @@ def topk_agreement(gpu_costs_list, ref_costs_list, k):
         hit += len(sg & sr)
         tot += kk
     return hit / max(tot, 1), hit, tot
+
+
+def pack_fp8(cm, queries, codes_list, device="cuda"):
+    """Lay queries out as for pack_queries, with the given e4m3 code arrays
+    (uint8 [S][N][40], one per query) as the schedule features."""
+    import torch
+    descs, pipes, codes, terms = [], [], [], []
+    po = so = to = co = 0
+    for q, c in zip(queries, codes_list):
+        S, N = c.shape[0], c.shape[1]
+        descs.append((S, N, po, so, to, co))
+        pipes.append(np.ascontiguousarray(q.pipe, np.float32).ravel())
+        codes.append(np.ascontiguousarray(c, np.uint8).ravel())
+        terms.append(np.ascontiguousarray(q.terms, np.float32).ravel())
+        po += S * 56
+        so += S * N * 40
+        to += S * N * 8
+        co += N
+    cat = lambda xs, dt, n: torch.from_numpy(np.concatenate(xs) if xs else np.zeros(n, dt)).to(device)  # noqa: E731
+    batch = cm.Batch(descs, cat(pipes, np.float32, 1), cat(codes, np.uint8, 16),
+                     cat(terms, np.float32, 4))
+    cost = torch.zeros(max(co, 1), dtype=torch.float32, device=device)
+    return batch, cost
+
+
+def gpu_costs_fp8(cm, model, queries, codes_list, ws=None):
+    import torch
+    own = ws is None
+    if own:
+        ws = workspace_for(cm, queries)
+    batch, cost = pack_fp8(cm, queries, codes_list)
+    cm.cm_eval_batch(model, "fp8", batch, ws, cost)
+    torch.cuda.synchronize()
+    c = cost.cpu().numpy()
+    out = [c[d[5]:d[5] + d[1]].copy() for d in batch.queries]
+    if own:
+        ws.close()
+    return out, batch, cost
+
+
+_FULL = {}
+
+
+def full_size_query(name="precision_65536x64"):
+    """The named workload's single query, drawn once per test process."""
+    from synth import workload
+    if name not in _FULL:
+        _FULL[name] = workload(name)
+    return _FULL[name]
+
+
+def sample_columns(n, idx_top, n_sample=512, seed=0):
+    """Candidate indices to check one by one: a seeded random sample plus the
+    GPU's own top-k."""
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(n, size=min(n, n_sample), replace=False)
+    return np.unique(np.concatenate([pick, np.asarray(idx_top)[np.asarray(idx_top) >= 0]]))

@@ -120,3 +120,21 @@ def test_server_arguments_are_rejected_before_device_work(cm):
     assert L.cm_serve_wait(None, 1, 10, None) == _lib.CM_EINVAL
     assert L.cm_server_get_stats(None, None) == _lib.CM_EINVAL
     assert L.cm_server_reset_stats(None) == _lib.CM_EINVAL
+
+
+def test_fp8_arguments_are_rejected_before_device_work(cm):
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    f = ctypes.c_float()
+    x = (ctypes.c_float * 64)()
+    assert L.cm_model_prepare_fp8(None, 1.0, 1.0) == _lib.CM_EINVAL
+    assert L.cm_fp8_calibrate(None, 1, x, x, ctypes.byref(f), ctypes.byref(f)) == _lib.CM_EINVAL
+    assert L.cm_fp8_encode(None, 0, 1.0, None, None) == _lib.CM_OK          # nothing to do
+    assert L.cm_fp8_encode(None, -1, 1.0, None, None) == _lib.CM_EINVAL
+    assert L.cm_fp8_encode(None, 4, 1.0, None, None) == _lib.CM_EINVAL
+    for s in (3.0, 0.0, -2.0, float("nan"), float("inf")):
+        assert L.cm_fp8_encode(x, 4, s, x, None) == _lib.CM_EINVAL, s
+    base = (ctypes.addressof(x) + 15) // 16 * 16
+    assert L.cm_fp8_encode(base, 8, 1.0, base + 16, None) == _lib.CM_EINVAL  # overlap
+    assert b"overlap" in L.cm_last_error()
+    assert L.cm_fp8_encode(base + 4, 4, 1.0, base + 64, None) == _lib.CM_EINVAL  # misaligned

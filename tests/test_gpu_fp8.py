@@ -1,0 +1,269 @@
+"""Parity of the FP8 (e4m3) form of the gfx950 library with the FP8 form of
+the FP64 oracle, through the C ABI.
+
+Both sides read the same e4m3 input codes (written by the oracle) and
+quantize weights and hidden activations the same way.  They differ in the
+arithmetic between the quantization points: FP64 in the oracle; on the GPU a
+float32 hoisted row and fp8 matrix instructions whose product sums carry an
+error of up to about 6.2e-4 of their largest product (measured on gfx950 over
+2 million random sums: the instruction does not round like float32).  So the
+test takes ACC_TOL = 2e-3 (about 3x that) and asks the oracle for each
+candidate's bound: the cost change if every product sum were off by ACC_TOL of
+its largest product and every hoisted row by 1e-5 of its terms' magnitudes
+(float32 rounding of its 80 terms is below 5e-6).  A hidden value that close
+to an e4m3 rounding midpoint may round to the neighbouring code; its swing
+passes through |W_2| to the cost.  Every candidate must satisfy
+  |gpu - oracle| <= bound + FP8_TOL * |oracle|,
+FP8_TOL = 1e-5 covering the float32 coefficient dot product and Kahan sum.
+Since that bound is loose, the typical candidate is also held to float32
+agreement: at least NO_FLIP_SHARE of them within FP8_TOL, median <= 2e-6.
+The encoder is compared code by code with the oracle's encoder; a code may
+differ (by one step) only where log1p(x) * s_in lies within float32 rounding
+of a midpoint, since the GPU takes log1p in float32.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synth import Query, draw_query, model_params, workload
+from tests import cmcases as cc
+from tests import gpucase as gc
+
+pytestmark = pytest.mark.gpu
+
+FP8_TOL = 1e-5
+ACC_TOL = 2e-3
+NO_FLIP_SHARE = 0.8
+IN_SCALE = 16.0   # log1p of the synthetic features stays below 28 = 448 / 16
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2012_07145_amd as cm
+    return cm
+
+
+@pytest.fixture(scope="module")
+def params():
+    return model_params(bias=True)
+
+
+def _e4m3_values(oracle):
+    return np.array([oracle.e4m3_decode(c) for c in range(256)])
+
+
+# ------------------------------------------------------------ encoder
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 4099, 1_000_003])
+def test_encode_matches_oracle(cm, oracle_mod, n):
+    import torch
+    rng = np.random.default_rng(n)
+    x = np.exp(rng.uniform(-14, 30, n)) * rng.choice([1.0, 1.0, 1.0, -1e-3], n)
+    x = x.astype(np.float32)
+    specials = np.array([0.0, -0.0, -1.0, -2.0, np.inf, -np.inf, np.nan, 1e-30, 3e38,
+                         -0.5, -0.999999], np.float32)
+    x[:min(n, specials.size)] = specials[:min(n, specials.size)]
+    for s in (1.0, IN_SCALE, 0.25):
+        xt = torch.from_numpy(x).cuda()
+        got = cm.cm_fp8_encode(xt, s).cpu().numpy()
+        want = oracle_mod.fp8_codes(x, s)
+        bad = np.nonzero(got != want)[0]
+        vals = _e4m3_values(oracle_mod)
+        for i in bad:  # only float32-rounding ties may differ, by one code
+            v = math.log1p(float(x[i])) * s
+            g, w = int(got[i]), int(want[i])
+            assert (g ^ w) < 0x80 and abs(g - w) == 1, (x[i], s, hex(g), hex(w))
+            mid = 0.5 * (vals[g] + vals[w])
+            assert abs(v - mid) <= 4e-7 * abs(mid), (x[i], s, v, mid)
+        assert bad.size <= max(2, n // 100_000), bad.size
+
+
+# ------------------------------------------------------------ hand examples
+def test_fp8_hand_examples_exact(cm, oracle_mod):
+    """Every quantization point of the hand examples is exact, so the FP8
+    form gives the hand-worked costs (the golden values) exactly."""
+    g = cc.load_golden("hand_examples.json")
+    m = cm.cm_model_create(cc.hand_params())
+    for act in (1.0, 4.0, 0.25):
+        cm.cm_model_prepare_fp8(m, 1.0, act)
+        for case in g["cases"]:
+            pipe, sched, terms = cc.hand_query(case["terms"], n_cands=70)
+            codes = oracle_mod.fp8_codes(sched, 1.0)
+            (c,), _, _ = gc.gpu_costs_fp8(cm, m, [Query(pipe, sched, terms)], [codes])
+            assert np.all(c == np.float32(case["cost"])), (act, case["name"], c[:4])
+    m.close()
+
+
+def test_fp8_hand_examples_quantized(cm, oracle_mod):
+    """The hand examples with inexact quantization points: hidden unit 3.1
+    rounds to 3 (cost 630 instead of 631); log1p(x) = 1.1 rounds to 1.125
+    (cost 9 instead of 8.8)."""
+    case = cc.load_golden("hand_examples.json")["cases"][0]
+    m = cm.cm_model_create(cc.set_params(cc.hand_params(), {"b_1": [[0, 0.1]]}))
+    pipe, sched, terms = cc.hand_query(case["terms"], n_cands=40)
+    for act in (1.0, 4.0, 0.125):
+        cm.cm_model_prepare_fp8(m, 1.0, act)
+        (c,), _, _ = gc.gpu_costs_fp8(cm, m, [Query(pipe, sched, terms)],
+                                      [oracle_mod.fp8_codes(sched, 1.0)])
+        assert np.all(c == 630.0), (act, c[:4])
+    m.close()
+    m = cm.cm_model_create(cc.log_params("sched"))
+    pipe, sched, terms = cc.hand_query([[8, 0, 0, 0, 0, 0, 0, 0]], n_cands=33,
+                                       sched0=math.expm1(1.1))
+    for s in (1.0, 2.0, 0.5):
+        cm.cm_model_prepare_fp8(m, s, 1.0)
+        (c,), _, _ = gc.gpu_costs_fp8(cm, m, [Query(pipe, sched, terms)],
+                                      [oracle_mod.fp8_codes(sched, s)])
+        assert np.all(c == 9.0), (s, c[:4])
+    m.close()
+
+
+# ------------------------------------------------------------ random queries
+def _check_against_oracle(oracle_mod, params, act, q, codes, c):
+    ref, bound = oracle_mod.eval_query_fp8(params, IN_SCALE, act, q.pipe, codes, q.terms,
+                                           acc_tol=ACC_TOL)
+    c = np.asarray(c, np.float64)
+    assert np.array_equal(np.isnan(c), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    slack = bound[ok] + FP8_TOL * np.abs(ref[ok])
+    dev = np.abs(c[ok] - ref[ok])
+    rel = dev / np.abs(ref[ok])
+    print(f"fp8 parity: n={rel.size} within1e-5={np.mean(rel <= FP8_TOL):.4f} "
+          f"median={np.median(rel):.3g} max={rel.max():.3g} "
+          f"max_dev/slack={(dev / slack).max():.3g} median_bound={np.median(bound[ok] / np.abs(ref[ok])):.3g}")
+    assert np.all(dev <= slack), (int(np.argmax(dev - slack)), float((dev / slack).max()))
+    # the worst-case bound is loose (every hidden value near a midpoint counted
+    # as flipped, about 4% of the cost); in fact a hidden value flips about
+    # once in 5e4, so most candidates take no flip and agree to float32: at
+    # 120 stages x 32 units about 92% of them (NO_FLIP_SHARE leaves room)
+    assert np.mean(rel <= FP8_TOL) >= NO_FLIP_SHARE and np.median(rel) <= 2e-6, \
+        (np.mean(rel <= FP8_TOL), np.median(rel))
+    return ref
+
+
+@pytest.mark.parametrize("S,N", [(1, 1), (5, 31), (16, 64), (17, 65), (37, 1000), (120, 97)])
+@pytest.mark.parametrize("act", [1.0, 8.0])
+def test_fp8_against_oracle(cm, oracle_mod, params, S, N, act):
+    q = draw_query(np.random.default_rng(3000 + S * 7 + N), S, N)
+    codes = oracle_mod.fp8_codes(q.sched, IN_SCALE)
+    m = cm.cm_model_create(params)
+    cm.cm_model_prepare_fp8(m, IN_SCALE, act)
+    (c,), batch, cost_t = gc.gpu_costs_fp8(cm, m, [q], [codes])
+    _check_against_oracle(oracle_mod, params, act, q, codes, c)
+    k = min(32, max(1, N))
+    idx, val = gc.gpu_topk(cm, cost_t, batch, k)
+    gc.assert_select_bit_exact(oracle_mod, c, idx[0], val[0], k)
+    m.close()
+
+
+def test_fp8_nan_code_poisons_only_its_candidate(cm, oracle_mod, params):
+    q = draw_query(np.random.default_rng(77), 9, 70)
+    codes = oracle_mod.fp8_codes(q.sched, IN_SCALE)
+    m = cm.cm_model_create(params)
+    cm.cm_model_prepare_fp8(m, IN_SCALE, 8.0)
+    (clean,), _, _ = gc.gpu_costs_fp8(cm, m, [q], [codes])
+    bad = codes.copy()
+    bad[4, 3, 17] = 0x7F
+    bad[0, 66, 39] = 0xFF
+    (c,), _, _ = gc.gpu_costs_fp8(cm, m, [q], [bad])
+    ref = oracle_mod.eval_query_fp8(params, IN_SCALE, 8.0, q.pipe, bad, q.terms)
+    assert np.isnan(ref[3]) and np.isnan(ref[66])
+    assert np.isnan(c[3]) and np.isnan(c[66])
+    keep = np.ones(70, bool)
+    keep[[3, 66]] = False
+    assert np.array_equal(c[keep], clean[keep])
+    m.close()
+
+
+def test_fp8_ragged_batch_alone_equals_in_mix(cm, oracle_mod, params):
+    """17 ragged queries in one launch: bit-identical to each query alone and
+    to the hoist + hoisted-evaluation pair; every query within the parity bar."""
+    import torch
+    W = workload("ragged_17q")
+    codes = [oracle_mod.fp8_codes(q.sched, IN_SCALE) for q in W.queries]
+    m = cm.cm_model_create(params)
+    cm.cm_model_prepare_fp8(m, IN_SCALE, 8.0)
+    ws = gc.workspace_for(cm, W.queries)
+    mix, batch, cost_t = gc.gpu_costs_fp8(cm, m, W.queries, codes, ws)
+    for j, q in enumerate(W.queries):
+        (alone,), _, _ = gc.gpu_costs_fp8(cm, m, [q], [codes[j]])
+        assert np.array_equal(alone.view(np.uint32), mix[j].view(np.uint32)), j
+        _check_against_oracle(oracle_mod, params, 8.0, q, codes[j], mix[j])
+    U = torch.empty(sum(q.n_stages for q in W.queries) * 32 + 4, device="cuda")
+    cost2 = torch.zeros_like(cost_t)
+    cm.cm_hoist_stages(m, "fp8", batch, U)
+    cm.cm_eval_hoisted(m, "fp8", batch, U, ws, cost2)
+    torch.cuda.synchronize()
+    assert torch.equal(cost2.view(torch.int32), cost_t.view(torch.int32))
+    ws.close()
+    m.close()
+
+
+# ------------------------------------------------------------ host side
+def test_fp8_errors(cm, params):
+    import torch
+    m = cm.cm_model_create(params)
+    q = draw_query(np.random.default_rng(1), 2, 8)
+    batch, cost = gc.pack_fp8(cm, [q], [np.zeros((2, 8, 40), np.uint8)])
+    ws = gc.workspace_for(cm, [q])
+    with pytest.raises(cm.CmError) as e:
+        cm.cm_eval_batch(m, "fp8", batch, ws, cost)
+    assert e.value.status == -1 and "FP8" in str(e.value)
+    for bad in ((3.0, 1.0), (1.0, 0.0), (1.0, -2.0), (float("inf"), 1.0), (2.0 ** 70, 1.0)):
+        with pytest.raises(cm.CmError):
+            cm.cm_model_prepare_fp8(m, *bad)
+    cm.cm_model_prepare_fp8(m, 2.0, 0.5)
+    cm.cm_eval_batch(m, "fp8", batch, ws, cost)
+    x = torch.zeros(64, device="cuda")
+    out = torch.zeros(80, dtype=torch.uint8, device="cuda")
+    with pytest.raises(cm.CmError):
+        cm.cm_fp8_encode(x, 3.0, out)
+    with pytest.raises(cm.CmError):
+        cm.cm_fp8_encode(x[1:], 1.0, out)        # misaligned input
+    with pytest.raises(cm.CmError):
+        cm.cm_fp8_encode(x[:60], 1.0, out[1:])   # misaligned output
+    torch.cuda.synchronize()
+    ws.close()
+    m.close()
+
+
+def test_fp8_calibrate(cm, params):
+    """Scales are the largest powers of two leaving a factor 2 of headroom over
+    the sample's largest |log1p(x)| and largest ReLU'd hidden value, the
+    latter computed here from the model's definition in float64."""
+    from synth import unpack_params
+    q = draw_query(np.random.default_rng(9), 6, 50)
+    pipe_rows = np.repeat(q.pipe, 50, axis=0)
+    sched_rows = q.sched.reshape(-1, 40)
+    m = cm.cm_model_create(params)
+    s_in, s_h = cm.cm_fp8_calibrate(m, pipe_rows, sched_rows)
+    P = {k: v.astype(np.float64) for k, v in unpack_params(params).items()}
+    lx = np.log1p(sched_rows.astype(np.float64))
+    ep = np.log1p(pipe_rows.astype(np.float64)) @ P["W_p"].T + P["b_p"]
+    es = lx @ P["W_s"].T + P["b_s"]
+    h = np.concatenate([ep, es], axis=1) @ P["W_1"].T + P["b_1"]
+    for s, amax in ((s_in, np.abs(lx).max()), (s_h, max(h.max(), 0.0))):
+        assert math.frexp(s)[0] == 0.5
+        assert s * 2 * amax <= 448 < 2 * s * 2 * amax, (s, amax)
+    m.close()
+
+
+def test_fp8_full_size_sampled(cm, oracle_mod, params):
+    """65,536 candidates x 64 stages in one call: every cost is produced by
+    the GPU; 512 sampled candidates plus the GPU's top-32 are recomputed by the
+    oracle one by one and held to the parity bar; the selection is bit-exact
+    on the GPU's own scores."""
+    W = gc.full_size_query()
+    q = W.queries[0]
+    codes = oracle_mod.fp8_codes(q.sched, IN_SCALE)
+    m = cm.cm_model_create(params)
+    cm.cm_model_prepare_fp8(m, IN_SCALE, 8.0)
+    (c,), batch, cost_t = gc.gpu_costs_fp8(cm, m, [q], [codes])
+    idx, val = gc.gpu_topk(cm, cost_t, batch, W.k)
+    gc.assert_select_bit_exact(oracle_mod, c, idx[0], val[0], W.k)
+    pick = gc.sample_columns(q.n_cands, idx[0])
+    sub = Query(q.pipe, q.sched[:, pick], q.terms[:, pick])
+    _check_against_oracle(oracle_mod, params, 8.0, sub, codes[:, pick], c[pick])
+    m.close()

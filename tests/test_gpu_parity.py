@@ -109,6 +109,25 @@ def test_bf16_against_fp64_on_rounded_inputs(cm, oracle_mod, model, params, S, N
     gc.assert_select_bit_exact(oracle_mod, c, idx[0], val[0], k)
 
 
+def test_bf16_full_size_sampled(cm, oracle_mod):
+    """65,536 candidates x 64 stages in one call; 512 sampled candidates plus
+    the GPU's top-32 recomputed by the oracle on the bf16-rounded inputs; the
+    selection bit-exact on the GPU's own scores."""
+    W = gc.full_size_query()
+    q = W.queries[0]
+    params = model_params()
+    m = cm.cm_model_create(params)
+    (c,), batch, cost_t = gc.gpu_costs(cm, m, [q], "bf16")
+    idx, val = gc.gpu_topk(cm, cost_t, batch, W.k)
+    gc.assert_select_bit_exact(oracle_mod, c, idx[0], val[0], W.k)
+    pick = gc.sample_columns(q.n_cands, idx[0])
+    sub = gc.quantized(Query(q.pipe, q.sched[:, pick], q.terms[:, pick]))
+    ref = oracle_mod.eval_query(params, sub.pipe, sub.sched, sub.terms)
+    err = gc.rel_err(c[pick], ref)
+    assert err.max() <= BF16_TOL and np.median(err) <= BF16_MEDIAN_TOL, (err.max(), np.median(err))
+    m.close()
+
+
 def test_ragged_batch_alone_equals_in_mix(cm, oracle_mod):
     """17 ragged queries in one launch: each query's costs are bit-identical to
     the same query evaluated alone; selection bit-exact; agreement reported."""
