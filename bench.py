@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 65,536 x 64 bf16 / fp8 comparison")
     ap.add_argument("--slots", type=int, default=3, help="serving micro-batches in flight")
     ap.add_argument("--max-batch-queries", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +312,61 @@ def main():
                          f"evaluation + stable selection, {reps} passes in {dt:.1f} s"}
         log(f"cpu oracle: {cpu['value']:.0f} candidates/s on {cpu['cores']} threads")
 
+    # ------------------------------------------------------------ bf16 vs fp8
+    precision = None
+    if not args.no_precision:
+        W3 = workload("precision_65536x64")
+        q3 = W3.queries[0]
+        S3, N3 = q3.n_stages, q3.n_cands
+        log("precision_65536x64: FP64 oracle for the agreement figures")
+        ref3 = oracle.eval_query(params, q3.pipe, q3.sched, q3.terms)
+        top_ref = set(np.lexsort((np.arange(N3), ref3))[:K].tolist())
+        s_in, s_h = cm.cm_fp8_calibrate(model, np.repeat(q3.pipe, 256, axis=0),
+                                        q3.sched[:, :256].reshape(-1, 40))
+        cm.cm_model_prepare_fp8(model, s_in, s_h)
+        ws3 = cm.cm_workspace_create(1, S3, N3, S3 * N3, K)
+        i3 = torch.empty(K, dtype=torch.int32, device=dev)
+        v3 = torch.empty(K, device=dev)
+
+        def timed(fn, reps=30):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps * 1e3  # us
+
+        precision = {"workload": "precision_65536x64", "stages": S3, "candidates": N3,
+                     "rows": S3 * N3, "k": K, "fp8_scales": {"s_in": s_in, "s_h": s_h}}
+        for pname, row_bytes in (("bf16", 80 + 32), ("fp8", 40 + 32)):
+            b3, c3 = cm.pack_queries([q3], pname, dev, in_scale=s_in)
+            us_eval = timed(lambda: cm.cm_eval_batch(model, pname, b3, ws3, c3))
+            us_call = timed(lambda: (cm.cm_eval_batch(model, pname, b3, ws3, c3),
+                                     cm.cm_topk_per_query(c3, b3, K, ws3, i3, v3)))
+            g3 = c3.cpu().numpy()[:N3].astype(np.float64)
+            top = set(i3.cpu().numpy().tolist())
+            precision[pname] = {
+                "eval_us": us_eval, "eval_topk_us": us_call,
+                "rows_per_s": S3 * N3 / (us_eval * 1e-6),
+                "candidates_per_s": N3 / (us_call * 1e-6),
+                "eval_gb_per_s": S3 * N3 * row_bytes / (us_eval * 1e3),
+                "bytes_per_row": row_bytes,
+                "top32_agreement_vs_fp64": len(top & top_ref) / K,
+                "median_rel_err_vs_fp64": float(np.median(np.abs(g3 - ref3) / ref3))}
+            log(f"precision_65536x64 {pname}: eval {us_eval:.1f} us "
+                f"({precision[pname]['eval_gb_per_s']:.0f} GB/s), eval+top-k {us_call:.1f} us, "
+                f"top-32 agreement {len(top & top_ref)}/{K}")
+            del b3, c3
+        x3 = torch.from_numpy(np.ascontiguousarray(q3.sched).ravel()).to(dev)
+        codes3 = torch.empty(x3.numel(), dtype=torch.uint8, device=dev)
+        us_enc = timed(lambda: cm.cm_fp8_encode(x3, s_in, codes3))
+        precision["fp8_encode"] = {"us": us_enc, "gb_per_s": x3.numel() * 5 / (us_enc * 1e3)}
+        del x3, codes3
+        ws3.close()
+
     # ------------------------------------------------------------ fp32 plain
     fp32 = None
     if not args.no_fp32:
@@ -368,6 +425,7 @@ def main():
         "fp32_plain": fp32,
         "bf16_over_fp32_plain": None if fp32 is None else value / fp32["candidates_per_s"],
         "ragged_step": ragged,
+        "precision": precision,
         "serving_top32_agreement_vs_fp64": s_hit / s_tot,
         "serving_top32_hits": [s_hit, s_tot],
         "top32_agreement_vs_fp64": None if ragged is None else ragged["top32_agreement_vs_fp64"],
