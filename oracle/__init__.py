@@ -51,6 +51,9 @@ class Oracle:
         L.cmo_fp8_codes.restype = None
         L.cmo_fp8_codes.argtypes = [_f32p, ctypes.c_int64, ctypes.c_double,
                                     np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
+        L.cmo_freeze.restype = ctypes.c_int32
+        L.cmo_freeze.argtypes = [_f64p, ctypes.c_int32,
+                                 np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
         L.cmo_select.restype = ctypes.c_int32
         L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
         self.L = L
@@ -121,6 +124,15 @@ class Oracle:
                             int(nthreads))
         return (cost, bound) if bound is not None else cost
 
+    def freeze(self, stage_cost):
+        """Freeze flags (uint8[S]) of one candidate's per-stage costs."""
+        c = np.ascontiguousarray(stage_cost, dtype=np.float64).ravel()
+        out = np.empty(c.size, np.uint8)
+        rc = self.L.cmo_freeze(c, c.size, out)
+        if rc != 0:
+            raise ValueError(f"cmo_freeze failed ({rc})")
+        return out
+
     def select(self, cost, k: int):
         """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""
         cost = np.ascontiguousarray(cost, dtype=np.float64)
@@ -175,3 +187,7 @@ def e4m3_decode(code: int) -> float:
 
 def fp8_scale(amax: float) -> float:
     return lib().fp8_scale(amax)
+
+
+def freeze(stage_cost):
+    return lib().freeze(stage_cost)

@@ -388,3 +388,26 @@ int32_t cmo_select(const double *cost, int32_t N, int32_t k, int32_t *idx_out,
     free(it);
     return 0;
 }
+
+/* ---- freezing of the lowest-cost stages (Sec. 3.2) ---- */
+
+/* The stages of the kept schedule are ordered by their predicted cost, in the
+ * same total order as the beam (ascending, -0 == +0, NaN last, ties by lower
+ * stage index), and all but ceil(log2 S) of them, the cheapest, are frozen. */
+int32_t cmo_freeze(const double *stage_cost, int32_t S, uint8_t *frozen_out)
+{
+    if (S < 1) return -1;
+    cmo_item *it = (cmo_item *)malloc(sizeof(cmo_item) * (size_t)S);
+    if (!it) return -2;
+    for (int32_t s = 0; s < S; ++s) {
+        it[s].key = stage_cost[s];
+        it[s].idx = s;
+        it[s].nan = isnan(stage_cost[s]) ? 1 : 0;
+    }
+    qsort(it, (size_t)S, sizeof(cmo_item), item_cmp);
+    int32_t unfrozen = 0; /* ceil(log2 S) */
+    while (((int64_t)1 << unfrozen) < (int64_t)S) ++unfrozen;
+    for (int32_t j = 0; j < S; ++j) frozen_out[it[j].idx] = j < S - unfrozen ? 1 : 0;
+    free(it);
+    return 0;
+}

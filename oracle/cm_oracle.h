@@ -54,6 +54,11 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
 int32_t cmo_select(const double *cost, int32_t N, int32_t k, int32_t *idx_out,
                    double *val_out);
 
+/* Freezing (Sec. 3.2): frozen_out[s] = 1 for the S - ceil(log2 S) lowest-cost
+ * stages of one candidate (order as cmo_select, by stage index on ties), else
+ * 0.  Returns 0, or <0 on S < 1 / no memory. */
+int32_t cmo_freeze(const double *stage_cost, int32_t S, uint8_t *frozen_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@ import pytest
 import oracle
 from oracle import build as obuild
 from tests import test_oracle_fp8_pins as fp8pins
+from tests import test_oracle_freeze_pins as frpins
 from tests import test_oracle_pins as pins
 
 PIN_TESTS = [
@@ -41,6 +42,9 @@ PIN_TESTS = [
     fp8pins.test_fp8_form_close_to_fp64_model,
     fp8pins.test_fp8_input_codes,
     fp8pins.test_fp8_error_bound,
+    frpins.test_freeze_counts,
+    frpins.test_freeze_hand_cases,
+    frpins.test_freeze_brute_force,
 ]
 
 # (name, text in cm_oracle.c, replacement)
@@ -82,6 +86,10 @@ MUTANTS = [
      "bound += (flips + 0.0 * pmax) / s2"),
     ("fp8 bound ignores the hoisted row", "+ 1e-5 * uabs[s * H + h]) * act_scale;",
      "+ 0.0 * uabs[s * H + h]) * act_scale;"),
+    ("freeze leaves floor(log2 S) free", "while (((int64_t)1 << unfrozen) < (int64_t)S) ++unfrozen;",
+     "while (((int64_t)2 << unfrozen) <= (int64_t)S) ++unfrozen;"),
+    ("freeze takes the costliest stages", "frozen_out[it[j].idx] = j < S - unfrozen ? 1 : 0;",
+     "frozen_out[it[j].idx] = j >= unfrozen ? 1 : 0;"),
     ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
 ]
 
