@@ -180,6 +180,36 @@ cm_status cm_eval_batch(const cm_model *model, cm_precision precision,
                         const cm_batch *batch, cm_workspace *ws, float *cost_out,
                         cm_stream stream);
 
+/* cm_eval_batch that also writes every stage's predicted cost (the v_s that
+ * Sec. 5.2 sums over stages, as added to the stage sum):
+ *   stage_cost_out[terms_off / 8 + s * n_cands + i] = v_s(i),
+ * i.e. a [n_stages][n_cands] float32 array per query at one eighth of its terms
+ * offset (device pointer; terms_off must be a multiple of 8).  Costs and
+ * their bits are those of cm_eval_batch.  Errors as cm_eval_batch. */
+cm_status cm_eval_stages(const cm_model *model, cm_precision precision,
+                         const cm_batch *batch, cm_workspace *ws, float *cost_out,
+                         float *stage_cost_out, cm_stream stream);
+
+/* Freezing of low-cost stages (Sec. 3.2): after a pre-pass, the schedule
+ * options of the lowest-cost stages of the kept schedule are frozen, all but
+ * ceil(log2 S) of them (S = the query's n_stages; a non-integer log2 is
+ * rounded up, so at least one stage is frozen and, for S >= 2, at least one
+ * stays free).  For query q the kept candidate is c = cand[q * cand_stride]
+ * (device int32; e.g. idx_out of cm_topk_per_query with stride k for each
+ * beam's best); its stage costs are read from stage_cost as cm_eval_stages
+ * writes them.  Stages are ranked by ascending cost, equal costs by lower
+ * stage index, -0 equal to +0, NaN after every number; the first
+ * S - ceil(log2 S) are frozen.  Writes frozen_out[row] = 1 (frozen) or 0, one
+ * uint8 per stage, rows in batch order (query q's stage s at the sum of
+ * n_stages of queries 0..q-1, plus s; device).  A c outside [0, n_cands)
+ * freezes nothing.  Only n_stages, n_cands and terms_off of each descriptor
+ * are read.  Asynchronous on `stream`; allocates nothing.
+ * Errors: CM_EINVAL (bad descriptor, terms_off not a multiple of 8, NULL
+ * pointer, cand_stride < 1), CM_EDEVICE. */
+cm_status cm_freeze_stages(const float *stage_cost, const cm_batch *batch,
+                           const int32_t *cand, int64_t cand_stride, uint8_t *frozen_out,
+                           cm_stream stream);
+
 /* Per-stage hoist (Sec. 5.2): the algorithm features of a stage are shared by
  * every candidate of its query, so their share of the first layer is
  * computed once per stage:

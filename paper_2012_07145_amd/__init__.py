@@ -22,6 +22,7 @@ __all__ = [
     "cm_version", "pack_queries", "Step", "cm_step_create", "cm_step_destroy", "cm_step_run",
     "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
     "Server", "cm_server_create", "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
+    "cm_eval_stages", "cm_freeze_stages",
 ]
 
 PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16, "fp8": CM_FP8}
@@ -175,6 +176,22 @@ def cm_eval_batch(model: Model, precision, batch: Batch, ws: Workspace, cost_out
     prec = PRECISIONS.get(precision, precision)
     check(lib().cm_eval_batch(model.handle, int(prec), ctypes.byref(batch.c), ws.handle,
                               _ptr(cost_out), _stream_handle(stream)))
+
+
+def cm_eval_stages(model: Model, precision, batch: Batch, ws: Workspace, cost_out, stage_out,
+                   stream=None):
+    """cm_eval_batch that also writes each query's per-stage costs [S][N] into
+    stage_out (float32 device tensor) at terms_off / 8."""
+    prec = PRECISIONS.get(precision, precision)
+    check(lib().cm_eval_stages(model.handle, int(prec), ctypes.byref(batch.c), ws.handle,
+                               _ptr(cost_out), _ptr(stage_out), _stream_handle(stream)))
+
+
+def cm_freeze_stages(stage_cost, batch: Batch, cand, cand_stride, frozen_out, stream=None):
+    """Freeze flags (uint8 device tensor, one per stage in batch order) of the
+    kept candidate cand[q * cand_stride] of every query."""
+    check(lib().cm_freeze_stages(_ptr(stage_cost), ctypes.byref(batch.c), _ptr(cand),
+                                 int(cand_stride), _ptr(frozen_out), _stream_handle(stream)))
 
 
 def cm_hoist_stages(model: Model, precision, batch: Batch, U_out, stream=None):

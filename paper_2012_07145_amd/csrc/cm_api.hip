@@ -388,6 +388,7 @@ void fill_eval_launch(cm::EvalLaunch &L, const cm_batch *b, int32_t g0, int32_t 
         e.hrow0 = (int32_t)hrow;
         e.task0 = (int32_t)task;
         e.parts = stage_parts(Q.n_stages);
+        e.stage_off = Q.terms_off / C;
         hrow += Q.n_stages;
         if (prec == CM_FP32) {
             task += cdiv(Q.n_cands, 64);
@@ -435,7 +436,7 @@ cm_status hoist_impl(const cm_model *M, cm_precision prec, const cm_batch *b, fl
 }
 
 cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, const float *U,
-                    const cm::Workspace &w, float *cost_out, hipStream_t s)
+                    const cm::Workspace &w, float *cost_out, float *stage_out, hipStream_t s)
 {
     using namespace cm;
     int64_t stage_prefix = 0;
@@ -444,13 +445,14 @@ cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, con
         EvalLaunch L;
         fill_eval_launch(L, b, g0, ng, stage_prefix, prec);
         if (prec == CM_FP32)
-            CM_HIP(launch_eval_fp32(L, M->m, (const float *)b->sched, b->terms, U, cost_out, s));
+            CM_HIP(launch_eval_fp32(L, M->m, (const float *)b->sched, b->terms, U, cost_out,
+                                    stage_out, s));
         else if (prec == CM_FP8)
             CM_HIP(launch_eval_fp8(L, M->m, (const uint8_t *)b->sched, b->terms, U, cost_out,
-                                   s));
+                                   stage_out, s));
         else
             CM_HIP(launch_eval_bf16(L, M->m, (const uint16_t *)b->sched, b->terms, U, cost_out,
-                                    s));
+                                    stage_out, s));
         stage_prefix += L.nstages;
     }
     return CM_OK;
@@ -503,7 +505,7 @@ cm_status cm_eval_hoisted(const cm_model *M, cm_precision prec, const cm_batch *
     if (st != CM_OK) return st;
     if (cands == 0) return CM_OK;
     if (!U || !aligned(U, 16)) return fail(CM_EINVAL, "U is NULL or not 16-byte aligned");
-    return eval_impl(M, prec, b, U, W->w, cost_out, (hipStream_t)stream);
+    return eval_impl(M, prec, b, U, W->w, cost_out, nullptr, (hipStream_t)stream);
 }
 
 cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
@@ -515,7 +517,70 @@ cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
     if (cands == 0) return CM_OK;
     hipStream_t s = (hipStream_t)stream;
     if ((st = hoist_impl(M, prec, b, W->w.d_U, s)) != CM_OK) return st;
-    return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, s);
+    return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, nullptr, s);
+}
+
+cm_status cm_eval_stages(const cm_model *M, cm_precision prec, const cm_batch *b,
+                         cm_workspace *W, float *cost_out, float *stage_cost_out,
+                         cm_stream stream)
+{
+    int64_t cands = 0;
+    cm_status st = check_eval(M, prec, b, W, cost_out, &cands);
+    if (st != CM_OK) return st;
+    for (int32_t q = 0; q < b->n_queries; ++q)
+        if (b->queries[q].terms_off % cm::C != 0)
+            return fail(CM_EINVAL, "query %d: terms_off %lld is not a multiple of 8", q,
+                        (long long)b->queries[q].terms_off);
+    if (cands == 0) return CM_OK;
+    if (!stage_cost_out) return fail(CM_EINVAL, "stage_cost_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = hoist_impl(M, prec, b, W->w.d_U, s)) != CM_OK) return st;
+    return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, stage_cost_out, s);
+}
+
+cm_status cm_freeze_stages(const float *stage_cost, const cm_batch *b, const int32_t *cand,
+                           int64_t cand_stride, uint8_t *frozen_out, cm_stream stream)
+{
+    using namespace cm;
+    if (!b) return fail(CM_EINVAL, "batch is NULL");
+    if (b->n_queries < 0) return fail(CM_EINVAL, "n_queries < 0");
+    if (b->n_queries > 0 && !b->queries) return fail(CM_EINVAL, "queries is NULL");
+    if (b->n_queries == 0) return CM_OK;
+    if (cand_stride < 1) return fail(CM_EINVAL, "cand_stride %lld < 1", (long long)cand_stride);
+    if (!cand || !frozen_out) return fail(CM_EINVAL, "cand or frozen_out is NULL");
+    int64_t cands = 0, stages = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) {
+        const cm_query &Q = b->queries[q];
+        if (Q.n_stages < 1) return fail(CM_EINVAL, "query %d: n_stages %d < 1", q, Q.n_stages);
+        if (Q.n_cands < 0) return fail(CM_EINVAL, "query %d: n_cands %d < 0", q, Q.n_cands);
+        stages += Q.n_stages;
+        if (Q.terms_off < 0 || Q.terms_off % C != 0)
+            return fail(CM_EINVAL, "query %d: terms_off %lld is not a non-negative multiple of 8",
+                        q, (long long)Q.terms_off);
+        cands += Q.n_cands;
+    }
+    if (cands > 0 && !stage_cost) return fail(CM_EINVAL, "stage_cost is NULL");
+    if (stages > INT32_MAX) return fail(CM_E2BIG, "too many stages");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t flag = 0;
+    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
+        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
+        FreezeLaunch L;
+        std::memset(&L, 0, sizeof L);
+        L.nq = ng;
+        for (int32_t j = 0; j < ng; ++j) {
+            const cm_query &Q = b->queries[g0 + j];
+            FreezeQ &f = L.q[j];
+            f.S = Q.n_stages;
+            f.N = Q.n_cands;
+            f.stage_off = Q.terms_off / C;
+            f.flag_off = flag;
+            f.cand_q = g0 + j;
+            flag += Q.n_stages;
+        }
+        CM_HIP(launch_freeze(L, stage_cost, cand, cand_stride, frozen_out, s));
+    }
+    return CM_OK;
 }
 
 cm_status cm_topk_per_query(const float *cost, const cm_batch *b, int32_t k, cm_workspace *W,

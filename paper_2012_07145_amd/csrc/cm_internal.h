@@ -90,6 +90,7 @@ struct EvalQ {
     int32_t task0;     // first workgroup (bf16) or thread block (fp32) of this query
     int32_t parts;     // stage parts P (bf16)
     int32_t pad;
+    int64_t stage_off; // offset (floats) of this query's per-stage costs [S][N] (terms_off / 8)
 };
 
 struct EvalLaunch {
@@ -98,6 +99,19 @@ struct EvalLaunch {
     int32_t nstages;   // hoist blocks
     int32_t pad;
     EvalQ q[QMAX];
+};
+
+struct FreezeQ {
+    int32_t S, N;
+    int64_t stage_off;  // per-stage costs [S][N] of the query (floats)
+    int64_t flag_off;   // its S flags in the output (batch order)
+    int64_t cand_q;     // index of the query in the caller's batch (cand[cand_q * stride])
+};
+
+struct FreezeLaunch {
+    int32_t nq;
+    int32_t pad;
+    FreezeQ q[QMAX];
 };
 
 struct TopkQ {
@@ -196,13 +210,19 @@ const uint64_t *step_clock(const cm_step *S);
 hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, float scale,
                         const float *pipe, float *U, hipStream_t st);
 hipError_t launch_eval_fp8(const EvalLaunch &L, const Model &m, const uint8_t *codes,
-                           const float *terms, const float *U, float *cost, hipStream_t st);
+                           const float *terms, const float *U, float *cost, float *stage,
+                           hipStream_t st);
 hipError_t launch_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t *codes,
                              hipStream_t st);
+// stage: per-stage costs [S][N] at each query's stage_off, or nullptr.
 hipError_t launch_eval_fp32(const EvalLaunch &L, const Model &m, const float *sched,
-                            const float *terms, const float *U, float *cost, hipStream_t st);
+                            const float *terms, const float *U, float *cost, float *stage,
+                            hipStream_t st);
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
-                            const float *terms, const float *U, float *cost, hipStream_t st);
+                            const float *terms, const float *U, float *cost, float *stage,
+                            hipStream_t st);
+hipError_t launch_freeze(const FreezeLaunch &L, const float *stage, const int32_t *cand,
+                         int64_t cand_stride, uint8_t *frozen, hipStream_t st);
 hipError_t launch_topk(const TopkLaunch &L, const float *cost, uint64_t *tpart, int32_t *tcnt,
                        int32_t *idx_out, float *val_out, hipStream_t st);
 hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m, int grid,

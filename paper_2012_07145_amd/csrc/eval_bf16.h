@@ -188,9 +188,10 @@ __device__ inline void refill_u(float4 *ur, const float4 *ug, int s, int n, int 
 
 // One stage of 32 candidates: both dense layers on the matrix cores, the
 // coefficient dot product with the cost terms, and the compensated sum.
-__device__ __forceinline__ void stage_math(const StageIn &in, const float4 *us, int hf,
-                                           const Weights &w, const Pairs &kp, float &sum,
-                                           float &comp)
+// Returns the stage's cost (in every lane of the candidate).
+__device__ __forceinline__ float stage_math(const StageIn &in, const float4 *us, int hf,
+                                            const Weights &w, const Pairs &kp, float &sum,
+                                            float &comp)
 {
     // first layer: accumulator starts from U[s]; register g*4+j holds
     // hidden unit g*8 + hf*4 + j
@@ -242,7 +243,9 @@ __device__ __forceinline__ void stage_math(const StageIn &in, const float4 *us, 
     v = fmaf(relu(acc2[2] + w.b2v[2]), in.t.z, v);
     v = fmaf(relu(acc2[3] + w.b2v[3]), in.t.w, v);
     if (invalid) v = __builtin_nanf("");
-    kahan_add(sum, comp, add_halves(v));
+    const float vs = add_halves(v);
+    kahan_add(sum, comp, vs);
+    return vs;
 }
 
 // Load this lane's packed operands of both layers (held for the whole wave).
@@ -271,6 +274,7 @@ struct QueryView {
     const float *t;     // cost terms [S][N][8]
     const float *u;     // hoisted rows [S][32]
     float *cost;        // [N]
+    float *stage;       // per-stage costs [S][N] (only with kStage)
     int S, N, P;
 };
 
@@ -284,8 +288,9 @@ struct GroupShared {
 // candidates, every wave one (tile, stage part).  Every thread of the
 // EVAL_WAVES-wave workgroup must call this with the same arguments (it
 // synchronises the workgroup when P > 1).  kShared: the costs are read by
-// another workgroup of the same launch (coherent stores).
-template <bool kShared>
+// another workgroup of the same launch (coherent stores).  kStage: also write
+// every stage's cost to Q.stage[s][i].
+template <bool kShared, bool kStage = false>
 __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wave, int lane,
                                            const Weights &w, const Pairs &kp, GroupShared &sh)
 {
@@ -334,7 +339,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             load_stage(B, xr, tr, xsoff, tsoff, xo, x2o, to);
             // keep the loads here, ahead of their use
             asm volatile("" ::: "memory");
-            stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            const float va = stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
             if (s + 1 >= s1) break;
 
             if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
@@ -344,7 +350,9 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             }
             load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
             asm volatile("" ::: "memory");
-            stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            const float vb =
+                stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
         }
     }
 

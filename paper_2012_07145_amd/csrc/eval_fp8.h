@@ -45,6 +45,7 @@ struct QueryView8 {
     const float *t;    // cost terms [S][N][8]
     const float *u;    // hoisted rows [S][32], already times s_h
     float *cost;       // [N]
+    float *stage;      // per-stage costs [S][N] (only with kStage)
     int S, N, P;
 };
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -92,8 +93,8 @@ __device__ inline void load_stage8(StageIn8 &in, __amdgpu_buffer_rsrc_t xr,
     in.t = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, 0));
 }
 
-__device__ __forceinline__ void stage_math8(const StageIn8 &in, const float4 *us, int hf,
-                                            const Weights8 &w, float &sum, float &comp)
+__device__ __forceinline__ float stage_math8(const StageIn8 &in, const float4 *us, int hf,
+                                             const Weights8 &w, float &sum, float &comp)
 {
     i32x8 B;
     B[0] = (int)in.x0.x;
@@ -138,12 +139,14 @@ __device__ __forceinline__ void stage_math8(const StageIn8 &in, const float4 *us
     v = fmaf(relu(fmaf(acc2[2], w.r2, w.b2v[2])), in.t.z, v);
     v = fmaf(relu(fmaf(acc2[3], w.r2, w.b2v[3])), in.t.w, v);
     if (invalid) v = __builtin_nanf("");
-    kahan_add(sum, comp, add_halves(v));
+    const float vs = add_halves(v);
+    kahan_add(sum, comp, vs);
+    return vs;
 }
 
 // eval_group of the FP8 form (see eval_bf16.h for the work split).  Q.x
 // points at the query's code bytes [S][N][40].
-template <bool kShared>
+template <bool kShared, bool kStage = false>
 __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int wave, int lane,
                                             const Weights8 &w, bf16eval::GroupShared &sh)
 {
@@ -181,7 +184,8 @@ __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int 
             }
             load_stage8(B, xr, tr, xsoff, tsoff, xo, to);
             asm volatile("" ::: "memory");
-            stage_math8(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, sum, comp);
+            const float va = stage_math8(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, sum, comp);
+            if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
             if (s + 1 >= s1) break;
 
             if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
@@ -191,7 +195,9 @@ __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int 
             }
             load_stage8(A, xr, tr, xsoff, tsoff, xo, to);
             asm volatile("" ::: "memory");
-            stage_math8(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, sum, comp);
+            const float vb =
+                stage_math8(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, sum, comp);
+            if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
         }
     }
 

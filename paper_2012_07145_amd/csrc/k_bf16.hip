@@ -17,9 +17,10 @@ __device__ inline int find_task_query(const EvalLaunch &L, int t)
     return q;
 }
 
+template <bool kStage>
 __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_eval_bf16(
     EvalLaunch L, const Bf16Pack *__restrict__ pk, const uint16_t *sched, const float *terms,
-    const float *__restrict__ U, float *__restrict__ cost)
+    const float *__restrict__ U, float *__restrict__ cost, float *__restrict__ stage)
 {
     __shared__ GroupShared sh;
     const int lane = threadIdx.x & 63;
@@ -32,22 +33,28 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     Q.t = terms + E.terms_off;
     Q.u = U + E.u_off;
     Q.cost = cost + E.cost_off;
+    Q.stage = kStage ? stage + E.stage_off : nullptr;
     Q.S = E.S;
     Q.N = E.N;
     Q.P = E.parts;
     const Weights w = load_weights(pk, lane);
     const Pairs kp = make_pairs();
-    eval_group<false>(Q, blockIdx.x - E.task0, wave, lane, w, kp, sh);
+    eval_group<false, kStage>(Q, blockIdx.x - E.task0, wave, lane, w, kp, sh);
 }
 
 }  // namespace
 
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
-                            const float *terms, const float *U, float *cost, hipStream_t st)
+                            const float *terms, const float *U, float *cost, float *stage,
+                            hipStream_t st)
 {
     if (L.ntasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_eval_bf16, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L, m.d_bf16,
-                       sched, terms, U, cost);
+    if (stage)
+        hipLaunchKernelGGL(k_eval_bf16<true>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
+                           m.d_bf16, sched, terms, U, cost, stage);
+    else
+        hipLaunchKernelGGL(k_eval_bf16<false>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
+                           m.d_bf16, sched, terms, U, cost, stage);
     return hipGetLastError();
 }
 

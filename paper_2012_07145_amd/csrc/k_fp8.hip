@@ -19,9 +19,10 @@ __device__ inline int find_task_query(const EvalLaunch &L, int t)
     return q;
 }
 
+template <bool kStage>
 __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_eval_fp8(
     EvalLaunch L, const Fp8Pack *__restrict__ pk, const uint8_t *codes, const float *terms,
-    const float *__restrict__ U, float *__restrict__ cost)
+    const float *__restrict__ U, float *__restrict__ cost, float *__restrict__ stage)
 {
     __shared__ bf16eval::GroupShared sh;
     const int lane = threadIdx.x & 63;
@@ -33,11 +34,12 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     Q.t = terms + E.terms_off;
     Q.u = U + E.u_off;
     Q.cost = cost + E.cost_off;
+    Q.stage = kStage ? stage + E.stage_off : nullptr;
     Q.S = E.S;
     Q.N = E.N;
     Q.P = E.parts;
     const Weights8 w = load_weights8(pk, lane);
-    eval_group8<false>(Q, blockIdx.x - E.task0, wave, lane, w, sh);
+    eval_group8<false, kStage>(Q, blockIdx.x - E.task0, wave, lane, w, sh);
 }
 
 // e4m3 code of v: NaN -> 0x7F, magnitudes beyond 448 saturate (the
@@ -84,11 +86,16 @@ __global__ __launch_bounds__(256) void k_fp8_encode(const float *__restrict__ x,
 }  // namespace
 
 hipError_t launch_eval_fp8(const EvalLaunch &L, const Model &m, const uint8_t *codes,
-                           const float *terms, const float *U, float *cost, hipStream_t st)
+                           const float *terms, const float *U, float *cost, float *stage,
+                           hipStream_t st)
 {
     if (L.ntasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_eval_fp8, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L, m.d_fp8,
-                       codes, terms, U, cost);
+    if (stage)
+        hipLaunchKernelGGL(k_eval_fp8<true>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
+                           m.d_fp8, codes, terms, U, cost, stage);
+    else
+        hipLaunchKernelGGL(k_eval_fp8<false>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
+                           m.d_fp8, codes, terms, U, cost, stage);
     return hipGetLastError();
 }
 

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(64) void k_eval_fp32(EvalLaunch L, const float *__r
                                                   const float *__restrict__ sched,
                                                   const float *__restrict__ terms,
                                                   const float *__restrict__ U,
-                                                  float *__restrict__ cost)
+                                                  float *__restrict__ cost,
+                                                  float *__restrict__ stage)
 {
     const int q = find_query(L, blockIdx.x, false);
     const EvalQ Q = L.q[q];
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(64) void k_eval_fp32(EvalLaunch L, const float *__r
             const float c = a < 0.f ? 0.f : a;
             v = fmaf(c, tr[m], v);
         }
+        if (stage) stage[Q.stage_off + r] = v;
         // Kahan-compensated stage sum
         const float y = v - comp;
         const float t = sum + y;
@@ -179,11 +181,12 @@ hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m,
 }
 
 hipError_t launch_eval_fp32(const EvalLaunch &L, const Model &m, const float *sched,
-                            const float *terms, const float *U, float *cost, hipStream_t st)
+                            const float *terms, const float *U, float *cost, float *stage,
+                            hipStream_t st)
 {
     if (L.ntasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval_fp32, dim3(L.ntasks), dim3(64), 0, st, L, m.d_params, sched,
-                       terms, U, cost);
+                       terms, U, cost, stage);
     return hipGetLastError();
 }
 

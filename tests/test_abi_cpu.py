@@ -138,3 +138,21 @@ def test_fp8_arguments_are_rejected_before_device_work(cm):
     assert L.cm_fp8_encode(base, 8, 1.0, base + 16, None) == _lib.CM_EINVAL  # overlap
     assert b"overlap" in L.cm_last_error()
     assert L.cm_fp8_encode(base + 4, 4, 1.0, base + 64, None) == _lib.CM_EINVAL  # misaligned
+
+
+def test_stage_and_freeze_arguments_are_rejected_before_device_work(cm):
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    assert L.cm_eval_stages(None, 1, None, None, None, None, None) == _lib.CM_EINVAL
+    assert L.cm_freeze_stages(None, None, None, 1, None, None) == _lib.CM_EINVAL
+    q = (_lib.cm_query * 1)(_lib.cm_query(3, 2, 0, 0, 12, 0))
+    b = _lib.cm_batch(1, q, None, None, None)
+    buf = (ctypes.c_int32 * 8)()
+    assert L.cm_freeze_stages(buf, ctypes.byref(b), buf, 1, buf, None) == _lib.CM_EINVAL
+    assert b"multiple of 8" in L.cm_last_error()
+    q[0] = _lib.cm_query(3, 2, 0, 0, 16, 0)
+    assert L.cm_freeze_stages(buf, ctypes.byref(b), buf, 0, buf, None) == _lib.CM_EINVAL
+    assert L.cm_freeze_stages(buf, ctypes.byref(b), None, 1, buf, None) == _lib.CM_EINVAL
+    assert L.cm_freeze_stages(None, ctypes.byref(b), buf, 1, buf, None) == _lib.CM_EINVAL
+    q[0] = _lib.cm_query(0, 2, 0, 0, 16, 0)
+    assert L.cm_freeze_stages(buf, ctypes.byref(b), buf, 1, buf, None) == _lib.CM_EINVAL
