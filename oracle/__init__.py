@@ -54,6 +54,10 @@ class Oracle:
         L.cmo_freeze.restype = ctypes.c_int32
         L.cmo_freeze.argtypes = [_f64p, ctypes.c_int32,
                                  np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
+        _u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        L.cmo_penalize_f32.restype = None
+        L.cmo_penalize_f32.argtypes = [_f32p, _u64p, ctypes.c_int64, _u64p, ctypes.c_int64,
+                                       ctypes.c_float]
         L.cmo_select.restype = ctypes.c_int32
         L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
         self.L = L
@@ -133,6 +137,16 @@ class Oracle:
             raise ValueError(f"cmo_freeze failed ({rc})")
         return out
 
+    def penalize(self, cost, hashes, bad, penalty):
+        """float32 costs with penalty added where the hash is in bad."""
+        c = np.array(cost, dtype=np.float32).ravel()
+        h = np.ascontiguousarray(hashes, dtype=np.uint64).ravel()
+        b = np.ascontiguousarray(bad, dtype=np.uint64).ravel()
+        assert h.size == c.size
+        self.L.cmo_penalize_f32(c, h, c.size, b if b.size else np.zeros(1, np.uint64), b.size,
+                                float(penalty))
+        return c
+
     def select(self, cost, k: int):
         """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""
         cost = np.ascontiguousarray(cost, dtype=np.float64)
@@ -191,3 +205,7 @@ def fp8_scale(amax: float) -> float:
 
 def freeze(stage_cost):
     return lib().freeze(stage_cost)
+
+
+def penalize(cost, hashes, bad, penalty):
+    return lib().penalize(cost, hashes, bad, penalty)

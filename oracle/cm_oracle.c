@@ -411,3 +411,18 @@ int32_t cmo_freeze(const double *stage_cost, int32_t S, uint8_t *frozen_out)
     free(it);
     return 0;
 }
+
+/* ---- known-bad-state penalty (Sec. 4.5) ---- */
+
+/* A candidate whose hash is in the set of hashes already judged unpromising
+ * gets the penalty added to its cost.  The addition is float32 (the cost is
+ * the float32 value the beam ranks); the set is searched linearly. */
+void cmo_penalize_f32(float *cost, const uint64_t *hashes, int64_t N, const uint64_t *bad,
+                      int64_t n_bad, float penalty)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        int seen = 0;
+        for (int64_t j = 0; j < n_bad && !seen; ++j) seen = hashes[i] == bad[j];
+        if (seen) cost[i] = cost[i] + penalty;
+    }
+}

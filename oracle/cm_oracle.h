@@ -59,6 +59,11 @@ int32_t cmo_select(const double *cost, int32_t N, int32_t k, int32_t *idx_out,
  * 0.  Returns 0, or <0 on S < 1 / no memory. */
 int32_t cmo_freeze(const double *stage_cost, int32_t S, uint8_t *frozen_out);
 
+/* Known-bad-state penalty (Sec. 4.5): cost[i] += penalty (float32) where
+ * hashes[i] is one of bad[0, n_bad) (any order). */
+void cmo_penalize_f32(float *cost, const uint64_t *hashes, int64_t N, const uint64_t *bad,
+                      int64_t n_bad, float penalty);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ import oracle
 from oracle import build as obuild
 from tests import test_oracle_fp8_pins as fp8pins
 from tests import test_oracle_freeze_pins as frpins
+from tests import test_oracle_penalty_pins as penpins
 from tests import test_oracle_pins as pins
 
 PIN_TESTS = [
@@ -45,6 +46,9 @@ PIN_TESTS = [
     frpins.test_freeze_counts,
     frpins.test_freeze_hand_cases,
     frpins.test_freeze_brute_force,
+    penpins.test_penalty_hand_cases,
+    penpins.test_penalty_is_float32_addition,
+    penpins.test_penalty_moves_candidates_back,
 ]
 
 # (name, text in cm_oracle.c, replacement)
@@ -90,6 +94,10 @@ MUTANTS = [
      "while (((int64_t)2 << unfrozen) <= (int64_t)S) ++unfrozen;"),
     ("freeze takes the costliest stages", "frozen_out[it[j].idx] = j < S - unfrozen ? 1 : 0;",
      "frozen_out[it[j].idx] = j >= unfrozen ? 1 : 0;"),
+    ("penalty ignores the last bad hash", "for (int64_t j = 0; j < n_bad && !seen; ++j) seen",
+     "for (int64_t j = 0; j + 1 < n_bad && !seen; ++j) seen"),
+    ("penalty matches every hash", "for (int64_t j = 0; j < n_bad && !seen; ++j) seen = hashes[i] == bad[j];",
+     "for (int64_t j = 0; j < n_bad && !seen; ++j) seen = hashes[i] == bad[j] || n_bad > 0;"),
     ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
 ]
 
