@@ -190,6 +190,42 @@ cm_status cm_eval_stages(const cm_model *model, cm_precision precision,
                          const cm_batch *batch, cm_workspace *ws, float *cost_out,
                          float *stage_cost_out, cm_stream stream);
 
+/* Memoized feature rows (Sec. 3.3): featurizations are memoized and reused
+ * across the schedules that share a kernel, so many (stage, candidate) rows
+ * repeat.  cm_eval_batch over a row table: batch->sched points at a table of
+ * table_rows schedule-feature rows (40 values each, in the precision's
+ * storage: bfloat16 bits for CM_BF16, e4m3 codes for CM_FP8), and each
+ * query's sched_off is an offset into row_idx (device int32), which holds
+ * its [n_stages][n_cands] row numbers; row (s, i) is table row
+ * row_idx[sched_off + s * n_cands + i].  Cost terms stay per (stage,
+ * candidate) as in cm_eval_batch (they hold the featurization's components
+ * that are always recomputed).  Results are bit-identical to cm_eval_batch
+ * on the materialized rows.  A row number outside [0, table_rows) gives that
+ * candidate a NaN cost (the table is never read outside its bounds).
+ * table_rows * row bytes must stay below 4 GiB.  CM_FP32 is not supported.
+ * Errors: as cm_eval_batch, CM_EINVAL (table_rows, row_idx),
+ * CM_EUNSUPPORTED (CM_FP32). */
+cm_status cm_eval_indexed(const cm_model *model, cm_precision precision,
+                          const cm_batch *batch, const int32_t *row_idx, int64_t table_rows,
+                          cm_workspace *ws, float *cost_out, cm_stream stream);
+
+/* Known-bad-state penalty of the multi-pass search (Sec. 4.5): before
+ * selection, a candidate whose structural hash (at the depth of the current
+ * pass, computed by the caller) is among the hashes already judged
+ * unpromising gets `penalty` added to its predicted cost, which moves it back
+ * in the beam.  For every query, candidate i with hashes[cost_off + i] in
+ * bad_sorted[0, n_bad) gets cost[cost_off + i] += penalty (float32 addition,
+ * in place).  hashes (uint64), bad_sorted (uint64, ascending, duplicates
+ * allowed) and cost are device pointers.  The paper gives no magnitude for
+ * the penalty; any non-NaN float is accepted (+inf pushes such candidates
+ * behind every finite cost).  Only n_cands and cost_off of each descriptor
+ * are read.  Run cm_topk_per_query afterwards.  Asynchronous on `stream`;
+ * allocates nothing.  Errors: CM_EINVAL (bad descriptor, NULL pointer,
+ * n_bad < 0, NaN penalty), CM_EDEVICE. */
+cm_status cm_penalize_known_bad(const cm_batch *batch, const uint64_t *hashes,
+                                const uint64_t *bad_sorted, int64_t n_bad, float penalty,
+                                float *cost, cm_stream stream);
+
 /* Freezing of low-cost stages (Sec. 3.2): after a pre-pass, the schedule
  * options of the lowest-cost stages of the kept schedule are frozen, all but
  * ceil(log2 S) of them (S = the query's n_stages; a non-integer log2 is

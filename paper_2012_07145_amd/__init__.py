@@ -22,7 +22,7 @@ __all__ = [
     "cm_version", "pack_queries", "Step", "cm_step_create", "cm_step_destroy", "cm_step_run",
     "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
     "Server", "cm_server_create", "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
-    "cm_eval_stages", "cm_freeze_stages",
+    "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
 ]
 
 PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16, "fp8": CM_FP8}
@@ -192,6 +192,26 @@ def cm_freeze_stages(stage_cost, batch: Batch, cand, cand_stride, frozen_out, st
     kept candidate cand[q * cand_stride] of every query."""
     check(lib().cm_freeze_stages(_ptr(stage_cost), ctypes.byref(batch.c), _ptr(cand),
                                  int(cand_stride), _ptr(frozen_out), _stream_handle(stream)))
+
+
+def cm_penalize_known_bad(batch: Batch, hashes, bad_sorted, penalty, cost, stream=None):
+    """cost[cost_off + i] += penalty where hashes[cost_off + i] is in
+    bad_sorted (uint64 device tensors viewed as int64; bad_sorted ascending as
+    unsigned 64-bit values)."""
+    n_bad = 0 if bad_sorted is None else int(bad_sorted.numel())
+    check(lib().cm_penalize_known_bad(ctypes.byref(batch.c), _ptr(hashes), _ptr(bad_sorted),
+                                      n_bad, float(penalty), _ptr(cost), _stream_handle(stream)))
+
+
+def cm_eval_indexed(model: Model, precision, batch: Batch, row_idx, table_rows, ws: Workspace,
+                    cost_out, stream=None):
+    """cm_eval_batch over memoized rows: batch.sched is the row table,
+    row_idx (int32 device tensor) holds each query's row numbers at its
+    sched_off."""
+    prec = PRECISIONS.get(precision, precision)
+    check(lib().cm_eval_indexed(model.handle, int(prec), ctypes.byref(batch.c), _ptr(row_idx),
+                                int(table_rows), ws.handle, _ptr(cost_out),
+                                _stream_handle(stream)))
 
 
 def cm_hoist_stages(model: Model, precision, batch: Batch, U_out, stream=None):

@@ -436,7 +436,8 @@ cm_status hoist_impl(const cm_model *M, cm_precision prec, const cm_batch *b, fl
 }
 
 cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, const float *U,
-                    const cm::Workspace &w, float *cost_out, float *stage_out, hipStream_t s)
+                    const cm::Workspace &w, float *cost_out, float *stage_out, hipStream_t s,
+                    const int32_t *ridx = nullptr, uint32_t rows = 0)
 {
     using namespace cm;
     int64_t stage_prefix = 0;
@@ -449,10 +450,10 @@ cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, con
                                     stage_out, s));
         else if (prec == CM_FP8)
             CM_HIP(launch_eval_fp8(L, M->m, (const uint8_t *)b->sched, b->terms, U, cost_out,
-                                   stage_out, s));
+                                   stage_out, s, ridx, rows));
         else
             CM_HIP(launch_eval_bf16(L, M->m, (const uint16_t *)b->sched, b->terms, U, cost_out,
-                                    stage_out, s));
+                                    stage_out, s, ridx, rows));
         stage_prefix += L.nstages;
     }
     return CM_OK;
@@ -536,6 +537,68 @@ cm_status cm_eval_stages(const cm_model *M, cm_precision prec, const cm_batch *b
     hipStream_t s = (hipStream_t)stream;
     if ((st = hoist_impl(M, prec, b, W->w.d_U, s)) != CM_OK) return st;
     return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, stage_cost_out, s);
+}
+
+cm_status cm_eval_indexed(const cm_model *M, cm_precision prec, const cm_batch *b,
+                          const int32_t *row_idx, int64_t table_rows, cm_workspace *W,
+                          float *cost_out, cm_stream stream)
+{
+    using namespace cm;
+    if (prec == CM_FP32)
+        return fail(CM_EUNSUPPORTED, "memoized rows need CM_BF16 or CM_FP8");
+    int64_t cands = 0;
+    cm_status st = check_eval(M, prec, b, W, cost_out, &cands);
+    if (st != CM_OK) return st;
+    if (cands == 0) return CM_OK;
+    const int64_t row_bytes = prec == CM_FP8 ? FS : FS * 2;
+    if (table_rows < 1 || table_rows * row_bytes > (int64_t)UINT32_MAX - 256)
+        return fail(CM_EINVAL, "table_rows %lld outside [1, %lld]", (long long)table_rows,
+                    (long long)(((int64_t)UINT32_MAX - 256) / row_bytes));
+    if (!row_idx) return fail(CM_EINVAL, "row_idx is NULL");
+    if (!aligned(row_idx, 4)) return fail(CM_EINVAL, "row_idx must be 4-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = hoist_impl(M, prec, b, W->w.d_U, s)) != CM_OK) return st;
+    return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, nullptr, s, row_idx,
+                     (uint32_t)table_rows);
+}
+
+cm_status cm_penalize_known_bad(const cm_batch *b, const uint64_t *hashes,
+                                const uint64_t *bad_sorted, int64_t n_bad, float penalty,
+                                float *cost, cm_stream stream)
+{
+    using namespace cm;
+    if (!b) return fail(CM_EINVAL, "batch is NULL");
+    if (b->n_queries < 0) return fail(CM_EINVAL, "n_queries < 0");
+    if (b->n_queries > 0 && !b->queries) return fail(CM_EINVAL, "queries is NULL");
+    if (n_bad < 0) return fail(CM_EINVAL, "n_bad %lld < 0", (long long)n_bad);
+    if (n_bad > 0 && !bad_sorted) return fail(CM_EINVAL, "bad_sorted is NULL");
+    if (std::isnan(penalty)) return fail(CM_EINVAL, "penalty is NaN");
+    int64_t cands = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) {
+        const cm_query &Q = b->queries[q];
+        if (Q.n_cands < 0) return fail(CM_EINVAL, "query %d: n_cands %d < 0", q, Q.n_cands);
+        if (Q.cost_off < 0) return fail(CM_EINVAL, "query %d: negative cost_off", q);
+        cands += Q.n_cands;
+    }
+    if (cands == 0 || n_bad == 0) return CM_OK;
+    if (!hashes || !cost) return fail(CM_EINVAL, "hashes or cost is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t g0 = 0; g0 < b->n_queries; g0 += QMAX) {
+        const int32_t ng = std::min<int32_t>(QMAX, b->n_queries - g0);
+        PenaltyLaunch L;
+        std::memset(&L, 0, sizeof L);
+        L.nq = ng;
+        int64_t c0 = 0;
+        for (int32_t j = 0; j < ng; ++j) {
+            const cm_query &Q = b->queries[g0 + j];
+            L.q[j].N = Q.n_cands;
+            L.q[j].cost_off = Q.cost_off;
+            L.q[j].cand0 = c0;
+            c0 += Q.n_cands;
+        }
+        CM_HIP(launch_penalty(L, hashes, bad_sorted, n_bad, penalty, cost, s));
+    }
+    return CM_OK;
 }
 
 cm_status cm_freeze_stages(const float *stage_cost, const cm_batch *b, const int32_t *cand,

@@ -114,6 +114,19 @@ struct FreezeLaunch {
     FreezeQ q[QMAX];
 };
 
+struct PenaltyQ {
+    int32_t N;
+    int32_t pad;
+    int64_t cost_off;  // costs (and hashes) of the query
+    int64_t cand0;     // candidates of the launch's earlier queries
+};
+
+struct PenaltyLaunch {
+    int32_t nq;
+    int32_t pad;
+    PenaltyQ q[QMAX];
+};
+
 struct TopkQ {
     int32_t N;
     int32_t out_q;     // index of the query in the caller's batch
@@ -209,9 +222,11 @@ const uint64_t *step_clock(const cm_step *S);
 // Kernel launchers (one per translation unit).
 hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, float scale,
                         const float *pipe, float *U, hipStream_t st);
+// ridx, rows: memoized rows (sched is then a table of `rows` rows and each
+// query's sched_off locates its row numbers in ridx), or nullptr.
 hipError_t launch_eval_fp8(const EvalLaunch &L, const Model &m, const uint8_t *codes,
                            const float *terms, const float *U, float *cost, float *stage,
-                           hipStream_t st);
+                           hipStream_t st, const int32_t *ridx = nullptr, uint32_t rows = 0);
 hipError_t launch_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t *codes,
                              hipStream_t st);
 // stage: per-stage costs [S][N] at each query's stage_off, or nullptr.
@@ -220,9 +235,11 @@ hipError_t launch_eval_fp32(const EvalLaunch &L, const Model &m, const float *sc
                             hipStream_t st);
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
                             const float *terms, const float *U, float *cost, float *stage,
-                            hipStream_t st);
+                            hipStream_t st, const int32_t *ridx = nullptr, uint32_t rows = 0);
 hipError_t launch_freeze(const FreezeLaunch &L, const float *stage, const int32_t *cand,
                          int64_t cand_stride, uint8_t *frozen, hipStream_t st);
+hipError_t launch_penalty(const PenaltyLaunch &L, const uint64_t *hashes, const uint64_t *bad,
+                          int64_t n_bad, float penalty, float *cost, hipStream_t st);
 hipError_t launch_topk(const TopkLaunch &L, const float *cost, uint64_t *tpart, int32_t *tcnt,
                        int32_t *idx_out, float *val_out, hipStream_t st);
 hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m, int grid,

@@ -147,6 +147,7 @@ struct StageIn {
     uint4 x0, x1;
     uint2 x2;
     float4 t;
+    bool bad;  // memoized rows: the stage's row number is outside the table
 };
 
 // Buffer descriptor over n bytes at p (raw, untyped dword access; loads at
@@ -242,7 +243,7 @@ __device__ __forceinline__ float stage_math(const StageIn &in, const float4 *us,
     v = fmaf(relu(acc2[1] + w.b2v[1]), in.t.y, v);
     v = fmaf(relu(acc2[2] + w.b2v[2]), in.t.z, v);
     v = fmaf(relu(acc2[3] + w.b2v[3]), in.t.w, v);
-    if (invalid) v = __builtin_nanf("");
+    if (invalid || in.bad) v = __builtin_nanf("");
     const float vs = add_halves(v);
     kahan_add(sum, comp, vs);
     return vs;
@@ -275,6 +276,8 @@ struct QueryView {
     const float *u;     // hoisted rows [S][32]
     float *cost;        // [N]
     float *stage;       // per-stage costs [S][N] (only with kStage)
+    const int32_t *ridx;  // memoized rows: row numbers [S][N] into x (only with kIndexed)
+    uint32_t rows;        // rows in the table x (only with kIndexed)
     int S, N, P;
 };
 
@@ -289,8 +292,10 @@ struct GroupShared {
 // EVAL_WAVES-wave workgroup must call this with the same arguments (it
 // synchronises the workgroup when P > 1).  kShared: the costs are read by
 // another workgroup of the same launch (coherent stores).  kStage: also write
-// every stage's cost to Q.stage[s][i].
-template <bool kShared, bool kStage = false>
+// every stage's cost to Q.stage[s][i].  kIndexed: the feature row of (s, i)
+// is row Q.ridx[s][i] of the table Q.x (memoized rows); a row number outside
+// the table makes that stage's cost NaN.
+template <bool kShared, bool kStage = false, bool kIndexed = false>
 __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wave, int lane,
                                            const Weights &w, const Pairs &kp, GroupShared &sh)
 {
@@ -311,15 +316,30 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart;
     // a query's arrays stay below 4 GB (S <= 2^16 stages of N <= 2^16 rows is
     // far beyond any workload; the host rejects larger)
-    const uint32_t xstep = (uint32_t)Q.N * FS * 2;
+    const uint32_t xstep = kIndexed ? 0u : (uint32_t)Q.N * FS * 2;
     const uint32_t tstep = (uint32_t)Q.N * C * 4;
-    const __amdgpu_buffer_rsrc_t xr = buffer_over(Q.x, xstep * (uint32_t)Q.S);
+    // memoized rows: the table's rows * 80 bytes fit in 32 bits (host check)
+    const uint32_t xbytes = kIndexed ? Q.rows * (FS * 2) : xstep * (uint32_t)Q.S;
+    const __amdgpu_buffer_rsrc_t xr = buffer_over(Q.x, xbytes);
     const __amdgpu_buffer_rsrc_t tr = buffer_over(Q.t, tstep * (uint32_t)Q.S);
     uint32_t xsoff = (uint32_t)s0 * xstep;
     uint32_t tsoff = (uint32_t)s0 * tstep;
-    const uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
-    const uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
+    uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
+    uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
     const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
+    // memoized rows: the row number of the stage loaded next, read one stage
+    // ahead of its feature loads; a row outside the table reads past the
+    // buffer's end (zeros) and is flagged
+    int32_t rnext = 0;
+    bool bad = false;
+    auto point_at = [&](int32_t r) {
+        const bool ok = (uint32_t)r < Q.rows;
+        const uint32_t ro = ok ? (uint32_t)r * (FS * 2) : xbytes;
+        xo = ro + hf * 16;
+        x2o = ro + 64 + hf * 8;
+        bad = !ok;
+    };
+    auto row_of = [&](int s) { return Q.ridx[(int64_t)s * Q.N + ic]; };
     const float4 *ug = reinterpret_cast<const float4 *>(Q.u);
     // this wave's slice of LDS holds the hoisted rows of up to USTAGE stages
     float4 *ur = sh.u[wave];
@@ -329,14 +349,24 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
         // two register buffers alternate so that a stage's loads stay in
         // flight during the previous stage's arithmetic without copies
         StageIn A, B;
+        if (kIndexed) {
+            point_at(row_of(s0));
+            if (s0 + 1 < s1) rnext = row_of(s0 + 1);
+        }
         load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
+        A.bad = bad;
         for (int s = s0; s < s1; s += 2) {
             if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
             if (s + 1 < s1) {
                 xsoff += xstep;
                 tsoff += tstep;
+                if (kIndexed) {
+                    point_at(rnext);
+                    if (s + 2 < s1) rnext = row_of(s + 2);
+                }
             }
             load_stage(B, xr, tr, xsoff, tsoff, xo, x2o, to);
+            B.bad = bad;
             // keep the loads here, ahead of their use
             asm volatile("" ::: "memory");
             const float va = stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
@@ -347,8 +377,13 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             if (s + 2 < s1) {
                 xsoff += xstep;
                 tsoff += tstep;
+                if (kIndexed) {
+                    point_at(rnext);
+                    if (s + 3 < s1) rnext = row_of(s + 3);
+                }
             }
             load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
+            A.bad = bad;
             asm volatile("" ::: "memory");
             const float vb =
                 stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);

@@ -46,6 +46,8 @@ struct QueryView8 {
     const float *u;    // hoisted rows [S][32], already times s_h
     float *cost;       // [N]
     float *stage;      // per-stage costs [S][N] (only with kStage)
+    const int32_t *ridx;  // memoized rows: row numbers [S][N] into x (only with kIndexed)
+    uint32_t rows;        // rows in the table x (only with kIndexed)
     int S, N, P;
 };
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -82,6 +84,7 @@ struct StageIn8 {
     uint4 x0;     // code bytes 0..15 of this lane's 20
     uint32_t x1;  // bytes 16..19
     float4 t;
+    bool bad;     // memoized rows: the stage's row number is outside the table
 };
 
 __device__ inline void load_stage8(StageIn8 &in, __amdgpu_buffer_rsrc_t xr,
@@ -138,15 +141,16 @@ __device__ __forceinline__ float stage_math8(const StageIn8 &in, const float4 *u
     v = fmaf(relu(fmaf(acc2[1], w.r2, w.b2v[1])), in.t.y, v);
     v = fmaf(relu(fmaf(acc2[2], w.r2, w.b2v[2])), in.t.z, v);
     v = fmaf(relu(fmaf(acc2[3], w.r2, w.b2v[3])), in.t.w, v);
-    if (invalid) v = __builtin_nanf("");
+    if (invalid || in.bad) v = __builtin_nanf("");
     const float vs = add_halves(v);
     kahan_add(sum, comp, vs);
     return vs;
 }
 
 // eval_group of the FP8 form (see eval_bf16.h for the work split).  Q.x
-// points at the query's code bytes [S][N][40].
-template <bool kShared, bool kStage = false>
+// points at the query's code bytes [S][N][40], or with kIndexed at a table of
+// code rows that Q.ridx[s][i] numbers (memoized rows).
+template <bool kShared, bool kStage = false, bool kIndexed = false>
 __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int wave, int lane,
                                             const Weights8 &w, bf16eval::GroupShared &sh)
 {
@@ -161,28 +165,49 @@ __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int 
     const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
     const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
 
-    const uint32_t xstep = (uint32_t)Q.N * FS;
+    const uint32_t xstep = kIndexed ? 0u : (uint32_t)Q.N * FS;
     const uint32_t tstep = (uint32_t)Q.N * C * 4;
-    const __amdgpu_buffer_rsrc_t xr = buffer_over(Q.x, xstep * (uint32_t)Q.S);
+    const uint32_t xbytes = kIndexed ? Q.rows * FS : xstep * (uint32_t)Q.S;
+    const __amdgpu_buffer_rsrc_t xr = buffer_over(Q.x, xbytes);
     const __amdgpu_buffer_rsrc_t tr = buffer_over(Q.t, tstep * (uint32_t)Q.S);
     uint32_t xsoff = (uint32_t)s0 * xstep;
     uint32_t tsoff = (uint32_t)s0 * tstep;
-    const uint32_t xo = (uint32_t)ic * FS + hf * 20;  // code bytes 20*hf .. +20
+    uint32_t xo = (uint32_t)ic * FS + hf * 20;  // code bytes 20*hf .. +20
     const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
+    // memoized rows (as in the bf16 evaluator): row numbers read one stage
+    // ahead; a row outside the table reads zeros and is flagged
+    int32_t rnext = 0;
+    bool bad = false;
+    auto point_at = [&](int32_t r) {
+        const bool ok = (uint32_t)r < Q.rows;
+        xo = (ok ? (uint32_t)r * FS : xbytes) + hf * 20;
+        bad = !ok;
+    };
+    auto row_of = [&](int s) { return Q.ridx[(int64_t)s * Q.N + ic]; };
     const float4 *ug = reinterpret_cast<const float4 *>(Q.u);
     float4 *ur = sh.u[wave];
 
     float sum = 0.f, comp = 0.f;
     if (s0 < s1) {
         StageIn8 A, B;
+        if (kIndexed) {
+            point_at(row_of(s0));
+            if (s0 + 1 < s1) rnext = row_of(s0 + 1);
+        }
         load_stage8(A, xr, tr, xsoff, tsoff, xo, to);
+        A.bad = bad;
         for (int s = s0; s < s1; s += 2) {
             if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
             if (s + 1 < s1) {
                 xsoff += xstep;
                 tsoff += tstep;
+                if (kIndexed) {
+                    point_at(rnext);
+                    if (s + 2 < s1) rnext = row_of(s + 2);
+                }
             }
             load_stage8(B, xr, tr, xsoff, tsoff, xo, to);
+            B.bad = bad;
             asm volatile("" ::: "memory");
             const float va = stage_math8(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, sum, comp);
             if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
@@ -192,8 +217,13 @@ __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int 
             if (s + 2 < s1) {
                 xsoff += xstep;
                 tsoff += tstep;
+                if (kIndexed) {
+                    point_at(rnext);
+                    if (s + 3 < s1) rnext = row_of(s + 3);
+                }
             }
             load_stage8(A, xr, tr, xsoff, tsoff, xo, to);
+            A.bad = bad;
             asm volatile("" ::: "memory");
             const float vb =
                 stage_math8(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, sum, comp);

@@ -17,10 +17,11 @@ __device__ inline int find_task_query(const EvalLaunch &L, int t)
     return q;
 }
 
-template <bool kStage>
+template <bool kStage, bool kIndexed>
 __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_eval_bf16(
     EvalLaunch L, const Bf16Pack *__restrict__ pk, const uint16_t *sched, const float *terms,
-    const float *__restrict__ U, float *__restrict__ cost, float *__restrict__ stage)
+    const float *__restrict__ U, float *__restrict__ cost, float *__restrict__ stage,
+    const int32_t *__restrict__ ridx, uint32_t rows)
 {
     __shared__ GroupShared sh;
     const int lane = threadIdx.x & 63;
@@ -29,7 +30,10 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     const int q = find_task_query(L, blockIdx.x);
     const EvalQ &E = L.q[q];
     QueryView Q;
-    Q.x = sched + E.sched_off;
+    // memoized rows: sched is the row table and sched_off locates the row numbers
+    Q.x = kIndexed ? sched : sched + E.sched_off;
+    Q.ridx = kIndexed ? ridx + E.sched_off : nullptr;
+    Q.rows = rows;
     Q.t = terms + E.terms_off;
     Q.u = U + E.u_off;
     Q.cost = cost + E.cost_off;
@@ -39,22 +43,31 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     Q.P = E.parts;
     const Weights w = load_weights(pk, lane);
     const Pairs kp = make_pairs();
-    eval_group<false, kStage>(Q, blockIdx.x - E.task0, wave, lane, w, kp, sh);
+    eval_group<false, kStage, kIndexed>(Q, blockIdx.x - E.task0, wave, lane, w, kp, sh);
 }
 
 }  // namespace
 
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
                             const float *terms, const float *U, float *cost, float *stage,
-                            hipStream_t st)
+                            hipStream_t st, const int32_t *ridx, uint32_t rows)
 {
     if (L.ntasks == 0) return hipSuccess;
-    if (stage)
-        hipLaunchKernelGGL(k_eval_bf16<true>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
-                           m.d_bf16, sched, terms, U, cost, stage);
-    else
-        hipLaunchKernelGGL(k_eval_bf16<false>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
-                           m.d_bf16, sched, terms, U, cost, stage);
+    const dim3 g(L.ntasks), b(EVAL_WAVES * 64);
+    if (ridx) {
+        if (stage)
+            hipLaunchKernelGGL((k_eval_bf16<true, true>), g, b, 0, st, L, m.d_bf16, sched, terms,
+                               U, cost, stage, ridx, rows);
+        else
+            hipLaunchKernelGGL((k_eval_bf16<false, true>), g, b, 0, st, L, m.d_bf16, sched, terms,
+                               U, cost, stage, ridx, rows);
+    } else if (stage) {
+        hipLaunchKernelGGL((k_eval_bf16<true, false>), g, b, 0, st, L, m.d_bf16, sched, terms, U,
+                           cost, stage, ridx, rows);
+    } else {
+        hipLaunchKernelGGL((k_eval_bf16<false, false>), g, b, 0, st, L, m.d_bf16, sched, terms, U,
+                           cost, stage, ridx, rows);
+    }
     return hipGetLastError();
 }
 

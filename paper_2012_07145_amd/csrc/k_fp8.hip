@@ -19,10 +19,11 @@ __device__ inline int find_task_query(const EvalLaunch &L, int t)
     return q;
 }
 
-template <bool kStage>
+template <bool kStage, bool kIndexed>
 __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_eval_fp8(
     EvalLaunch L, const Fp8Pack *__restrict__ pk, const uint8_t *codes, const float *terms,
-    const float *__restrict__ U, float *__restrict__ cost, float *__restrict__ stage)
+    const float *__restrict__ U, float *__restrict__ cost, float *__restrict__ stage,
+    const int32_t *__restrict__ ridx, uint32_t rows)
 {
     __shared__ bf16eval::GroupShared sh;
     const int lane = threadIdx.x & 63;
@@ -30,7 +31,10 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     const int q = find_task_query(L, blockIdx.x);
     const EvalQ &E = L.q[q];
     QueryView8 Q;
-    Q.x = codes + E.sched_off;
+    // memoized rows: codes is the row table and sched_off locates the row numbers
+    Q.x = kIndexed ? codes : codes + E.sched_off;
+    Q.ridx = kIndexed ? ridx + E.sched_off : nullptr;
+    Q.rows = rows;
     Q.t = terms + E.terms_off;
     Q.u = U + E.u_off;
     Q.cost = cost + E.cost_off;
@@ -39,7 +43,7 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     Q.N = E.N;
     Q.P = E.parts;
     const Weights8 w = load_weights8(pk, lane);
-    eval_group8<false, kStage>(Q, blockIdx.x - E.task0, wave, lane, w, sh);
+    eval_group8<false, kStage, kIndexed>(Q, blockIdx.x - E.task0, wave, lane, w, sh);
 }
 
 // e4m3 code of v: NaN -> 0x7F, magnitudes beyond 448 saturate (the
@@ -87,15 +91,24 @@ __global__ __launch_bounds__(256) void k_fp8_encode(const float *__restrict__ x,
 
 hipError_t launch_eval_fp8(const EvalLaunch &L, const Model &m, const uint8_t *codes,
                            const float *terms, const float *U, float *cost, float *stage,
-                           hipStream_t st)
+                           hipStream_t st, const int32_t *ridx, uint32_t rows)
 {
     if (L.ntasks == 0) return hipSuccess;
-    if (stage)
-        hipLaunchKernelGGL(k_eval_fp8<true>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
-                           m.d_fp8, codes, terms, U, cost, stage);
-    else
-        hipLaunchKernelGGL(k_eval_fp8<false>, dim3(L.ntasks), dim3(EVAL_WAVES * 64), 0, st, L,
-                           m.d_fp8, codes, terms, U, cost, stage);
+    const dim3 g(L.ntasks), b(EVAL_WAVES * 64);
+    if (ridx) {
+        if (stage)
+            hipLaunchKernelGGL((k_eval_fp8<true, true>), g, b, 0, st, L, m.d_fp8, codes, terms, U,
+                               cost, stage, ridx, rows);
+        else
+            hipLaunchKernelGGL((k_eval_fp8<false, true>), g, b, 0, st, L, m.d_fp8, codes, terms, U,
+                               cost, stage, ridx, rows);
+    } else if (stage) {
+        hipLaunchKernelGGL((k_eval_fp8<true, false>), g, b, 0, st, L, m.d_fp8, codes, terms, U,
+                           cost, stage, ridx, rows);
+    } else {
+        hipLaunchKernelGGL((k_eval_fp8<false, false>), g, b, 0, st, L, m.d_fp8, codes, terms, U,
+                           cost, stage, ridx, rows);
+    }
     return hipGetLastError();
 }
 

@@ -156,3 +156,17 @@ def test_stage_and_freeze_arguments_are_rejected_before_device_work(cm):
     assert L.cm_freeze_stages(None, ctypes.byref(b), buf, 1, buf, None) == _lib.CM_EINVAL
     q[0] = _lib.cm_query(0, 2, 0, 0, 16, 0)
     assert L.cm_freeze_stages(buf, ctypes.byref(b), buf, 1, buf, None) == _lib.CM_EINVAL
+
+
+def test_penalty_arguments_are_rejected_before_device_work(cm):
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    q = (_lib.cm_query * 1)(_lib.cm_query(1, 4, 0, 0, 0, 0))
+    b = _lib.cm_batch(1, q, None, None, None)
+    buf = (ctypes.c_int64 * 8)()
+    assert L.cm_penalize_known_bad(None, buf, buf, 1, 1.0, buf, None) == _lib.CM_EINVAL
+    assert L.cm_penalize_known_bad(ctypes.byref(b), buf, buf, -1, 1.0, buf, None) == _lib.CM_EINVAL
+    assert L.cm_penalize_known_bad(ctypes.byref(b), buf, None, 2, 1.0, buf, None) == _lib.CM_EINVAL
+    assert L.cm_penalize_known_bad(ctypes.byref(b), buf, buf, 2, float("nan"), buf, None) == _lib.CM_EINVAL
+    assert L.cm_penalize_known_bad(ctypes.byref(b), None, buf, 2, 1.0, buf, None) == _lib.CM_EINVAL
+    assert L.cm_penalize_known_bad(ctypes.byref(b), None, None, 0, 1.0, None, None) == _lib.CM_OK
