@@ -58,6 +58,10 @@ class Oracle:
         L.cmo_penalize_f32.restype = None
         L.cmo_penalize_f32.argtypes = [_f32p, _u64p, ctypes.c_int64, _u64p, ctypes.c_int64,
                                        ctypes.c_float]
+        L.cmo_splitmix64.restype = ctypes.c_uint64
+        L.cmo_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.cmo_sample.restype = ctypes.c_int64
+        L.cmo_sample.argtypes = [_u64p, ctypes.c_int64, ctypes.c_uint64, _i32p]
         L.cmo_select.restype = ctypes.c_int32
         L.cmo_select.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, _i32p, _f64p]
         self.L = L
@@ -147,6 +151,19 @@ class Oracle:
                                 float(penalty))
         return c
 
+    def splitmix64(self, seed: int, i: int) -> int:
+        return int(self.L.cmo_splitmix64(seed & (2 ** 64 - 1), i))
+
+    def sample(self, hashes, seed: int):
+        """Representatives (ascending option indices) of the hash buckets."""
+        h = np.ascontiguousarray(hashes, dtype=np.uint64).ravel()
+        out = np.empty(max(1, h.size), np.int32)
+        n = self.L.cmo_sample(h if h.size else np.zeros(1, np.uint64), h.size,
+                              seed & (2 ** 64 - 1), out)
+        if n < 0:
+            raise ValueError(f"cmo_sample failed ({n})")
+        return out[:n].copy()
+
     def select(self, cost, k: int):
         """The k best (lowest cost) candidates: (idx int32[k], val float64[k])."""
         cost = np.ascontiguousarray(cost, dtype=np.float64)
@@ -209,3 +226,11 @@ def freeze(stage_cost):
 
 def penalize(cost, hashes, bad, penalty):
     return lib().penalize(cost, hashes, bad, penalty)
+
+
+def splitmix64(seed: int, i: int) -> int:
+    return lib().splitmix64(seed, i)
+
+
+def sample(hashes, seed: int):
+    return lib().sample(hashes, seed)

@@ -426,3 +426,73 @@ void cmo_penalize_f32(float *cost, const uint64_t *hashes, int64_t N, const uint
         if (seen) cost[i] = cost[i] + penalty;
     }
 }
+
+/* ---- hierarchical sampling (Sec. 3.1, Sec. 4.4) ---- */
+
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014; the public-domain
+ * reference generator): the state advances by the golden-ratio increment and
+ * each output is the state passed through a xorshift-multiply mix.  Output
+ * number i (from 0) of the stream started at `seed` depends only on
+ * (seed, i), which makes it a counter-based generator. */
+uint64_t cmo_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+typedef struct {
+    uint64_t hash;
+    uint32_t key;  /* the random draw: high 32 bits of the generator's output */
+    int32_t idx;
+} cmo_opt;
+
+static int opt_cmp(const void *a, const void *b)
+{
+    const cmo_opt *A = (const cmo_opt *)a, *B = (const cmo_opt *)b;
+    if (A->hash != B->hash) return A->hash < B->hash ? -1 : 1;
+    if (A->key != B->key) return A->key < B->key ? -1 : 1;
+    return A->idx < B->idx ? -1 : (A->idx > B->idx ? 1 : 0);
+}
+
+/* Options with equal structural hashes form a bucket; from a bucket of B
+ * options, max(1, ceil(log2 B)) representatives are drawn at random without
+ * replacement: the ones with the smallest random keys (ties by lower index),
+ * key i being drawn from output i of the generator seeded with `seed`.
+ * Writes the representatives' indices ascending to out_idx and returns how
+ * many there are (<0 on bad sizes / no memory). */
+int64_t cmo_sample(const uint64_t *hashes, int64_t n, uint64_t seed, int32_t *out_idx)
+{
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    cmo_opt *o = (cmo_opt *)malloc(sizeof(cmo_opt) * (size_t)n);
+    uint8_t *keep = (uint8_t *)calloc((size_t)n, 1);
+    if (!o || !keep) {
+        free(o);
+        free(keep);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        o[i].hash = hashes[i];
+        o[i].key = (uint32_t)(cmo_splitmix64(seed, (uint64_t)i) >> 32);
+        o[i].idx = (int32_t)i;
+    }
+    qsort(o, (size_t)n, sizeof(cmo_opt), opt_cmp);
+    for (int64_t b = 0; b < n;) {
+        int64_t e = b;
+        while (e < n && o[e].hash == o[b].hash) ++e;
+        const int64_t B = e - b;
+        int64_t reps = 0; /* ceil(log2 B), at least 1 */
+        while (((int64_t)1 << reps) < B) ++reps;
+        if (reps < 1) reps = 1;
+        for (int64_t j = b; j < b + reps && j < e; ++j) keep[o[j].idx] = 1;
+        b = e;
+    }
+    int64_t count = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (keep[i]) out_idx[count++] = (int32_t)i;
+    free(o);
+    free(keep);
+    return count;
+}

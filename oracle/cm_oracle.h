@@ -64,6 +64,14 @@ int32_t cmo_freeze(const double *stage_cost, int32_t S, uint8_t *frozen_out);
 void cmo_penalize_f32(float *cost, const uint64_t *hashes, int64_t N, const uint64_t *bad,
                       int64_t n_bad, float penalty);
 
+/* Hierarchical sampling (Sec. 3.1): SplitMix64 output i of the stream seeded
+ * with seed; and the representatives of the buckets of equal hashes,
+ * max(1, ceil(log2 B)) per bucket of B options with the smallest keys
+ * (high 32 bits of output i for option i, ties by index), written ascending
+ * to out_idx (capacity n).  Returns their count, or <0. */
+uint64_t cmo_splitmix64(uint64_t seed, uint64_t i);
+int64_t cmo_sample(const uint64_t *hashes, int64_t n, uint64_t seed, int32_t *out_idx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@ from oracle import build as obuild
 from tests import test_oracle_fp8_pins as fp8pins
 from tests import test_oracle_freeze_pins as frpins
 from tests import test_oracle_penalty_pins as penpins
+from tests import test_oracle_sample_pins as smpins
 from tests import test_oracle_pins as pins
 
 PIN_TESTS = [
@@ -49,6 +50,10 @@ PIN_TESTS = [
     penpins.test_penalty_hand_cases,
     penpins.test_penalty_is_float32_addition,
     penpins.test_penalty_moves_candidates_back,
+    smpins.test_splitmix64_reference_outputs,
+    smpins.test_representatives_per_bucket,
+    smpins.test_sample_brute_force,
+    smpins.test_draws_are_uniform,
 ]
 
 # (name, text in cm_oracle.c, replacement)
@@ -98,6 +103,12 @@ MUTANTS = [
      "for (int64_t j = 0; j + 1 < n_bad && !seen; ++j) seen"),
     ("penalty matches every hash", "for (int64_t j = 0; j < n_bad && !seen; ++j) seen = hashes[i] == bad[j];",
      "for (int64_t j = 0; j < n_bad && !seen; ++j) seen = hashes[i] == bad[j] || n_bad > 0;"),
+    ("splitmix64 wrong shift", "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
+     "z = (z ^ (z >> 28)) * 0x94D049BB133111EBull;"),
+    ("sample keeps floor(log2 B)", "while (((int64_t)1 << reps) < B) ++reps;",
+     "while (((int64_t)2 << reps) <= B) ++reps;"),
+    ("sample keeps the largest keys", "if (A->key != B->key) return A->key < B->key ? -1 : 1;",
+     "if (A->key != B->key) return A->key > B->key ? -1 : 1;"),
     ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
 ]
 
