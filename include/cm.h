@@ -190,6 +190,37 @@ cm_status cm_eval_stages(const cm_model *model, cm_precision precision,
                          const cm_batch *batch, cm_workspace *ws, float *cost_out,
                          float *stage_cost_out, cm_stream stream);
 
+/* Hierarchical sampling (Sec. 3.1, Sec. 4.4): before featurization and
+ * evaluation, the enumerated options of a query are grouped into buckets by
+ * their structural hash, and only a few random representatives of every
+ * bucket go on to the cost model: max(1, ceil(log2 B)) of a bucket of B
+ * options (log2 B rounded up, at least one), drawn without replacement.
+ * The draw is reproducible: option i gets the random key
+ *   key(i) = (SplitMix64 output i of the stream seeded with seeds[q]) >> 32
+ * (SplitMix64 of Steele, Lea and Flood, OOPSLA 2014: the state advances by
+ * 0x9E3779B97F4A7C15, outputs pass a xorshift-multiply mix), and a bucket's
+ * representatives are its members with the smallest keys, equal keys by
+ * lower index.
+ *
+ * A sampler owns the device scratch for up to max_queries queries and
+ * max_options options per call (about 60 bytes per option).  For query q of
+ * `batch` (only n_cands = its option count and cost_off are read),
+ * hashes[cost_off + i] (device uint64) is option i's structural hash; the
+ * representatives' indices are written ascending to sel_idx[cost_off + j]
+ * (device int32, room for n_cands) and their number to sel_count[q]
+ * (device).  seeds is a host array of n_queries seeds.  Asynchronous on
+ * `stream` (the descriptors are staged through pinned memory); allocates
+ * nothing.  One sampler serves one stream at a time.
+ * Errors: CM_EINVAL (NULL pointer, bad descriptor, wrong device), CM_E2BIG
+ * (more queries or options than the sampler holds), CM_ENOMEM (create),
+ * CM_EDEVICE. */
+typedef struct cm_sampler cm_sampler;
+cm_status cm_sampler_create(int32_t max_queries, int64_t max_options, cm_sampler **out);
+cm_status cm_sampler_destroy(cm_sampler *sampler);
+cm_status cm_sample_buckets(cm_sampler *sampler, const cm_batch *batch, const uint64_t *hashes,
+                            const uint64_t *seeds, int32_t *sel_idx, int32_t *sel_count,
+                            cm_stream stream);
+
 /* Memoized feature rows (Sec. 3.3): featurizations are memoized and reused
  * across the schedules that share a kernel, so many (stage, candidate) rows
  * repeat.  cm_eval_batch over a row table: batch->sched points at a table of

@@ -23,6 +23,7 @@ __all__ = [
     "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
     "Server", "cm_server_create", "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
+    "Sampler", "cm_sampler_create", "cm_sample_buckets",
 ]
 
 PRECISIONS = {"fp32": CM_FP32, "bf16": CM_BF16, "fp8": CM_FP8}
@@ -212,6 +213,43 @@ def cm_eval_indexed(model: Model, precision, batch: Batch, row_idx, table_rows, 
     check(lib().cm_eval_indexed(model.handle, int(prec), ctypes.byref(batch.c), _ptr(row_idx),
                                 int(table_rows), ws.handle, _ptr(cost_out),
                                 _stream_handle(stream)))
+
+
+class Sampler:
+    """Handle of a cm_sampler (device scratch of the hierarchical sampling)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle is not None:
+            check(lib().cm_sampler_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cm_sampler_create(max_queries, max_options) -> Sampler:
+    h = ctypes.c_void_p()
+    check(lib().cm_sampler_create(int(max_queries), int(max_options), ctypes.byref(h)))
+    return Sampler(h)
+
+
+def cm_sample_buckets(sampler: Sampler, batch: Batch, hashes, seeds, sel_idx, sel_count,
+                      stream=None):
+    """Representatives of every query's hash buckets into sel_idx (at
+    cost_off, ascending) and their counts into sel_count; seeds: one
+    unsigned 64-bit seed per query (host)."""
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).ravel())
+    if sd.size < batch.n_queries:
+        raise ValueError("one seed per query")
+    check(lib().cm_sample_buckets(sampler.handle, ctypes.byref(batch.c), _ptr(hashes),
+                                  sd.ctypes.data_as(ctypes.c_void_p), _ptr(sel_idx),
+                                  _ptr(sel_count), _stream_handle(stream)))
 
 
 def cm_hoist_stages(model: Model, precision, batch: Batch, U_out, stream=None):

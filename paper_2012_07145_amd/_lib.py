@@ -34,6 +34,7 @@ EXPORTS = (
     "cm_server_get_stats", "cm_server_reset_stats",
     "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
+    "cm_sampler_create", "cm_sampler_destroy", "cm_sample_buckets",
     "cm_last_error", "cm_version",
 )
 
@@ -160,6 +161,9 @@ def lib():
         L.cm_freeze_stages.argtypes = [vp, ctypes.POINTER(cm_batch), vp, i64, vp, vp]
         L.cm_penalize_known_bad.argtypes = [ctypes.POINTER(cm_batch), vp, vp, i64, fl, vp, vp]
         L.cm_eval_indexed.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, i64, vp, vp, vp]
+        L.cm_sampler_create.argtypes = [i32, i64, ctypes.POINTER(vp)]
+        L.cm_sampler_destroy.argtypes = [vp]
+        L.cm_sample_buckets.argtypes = [vp, ctypes.POINTER(cm_batch), vp, vp, vp, vp, vp]
         for f in ("cm_model_create", "cm_model_destroy", "cm_workspace_create",
                   "cm_workspace_destroy", "cm_eval_batch", "cm_hoist_stages",
                   "cm_eval_hoisted", "cm_topk_per_query", "cm_step_create",
@@ -170,7 +174,8 @@ def lib():
                   "cm_serve_wait", "cm_server_get_stats", "cm_server_reset_stats",
                   "cm_serve_submit_batch", "cm_serve_wait_all", "cm_model_prepare_fp8",
                   "cm_fp8_calibrate", "cm_fp8_encode", "cm_eval_stages", "cm_freeze_stages",
-                  "cm_penalize_known_bad", "cm_eval_indexed"):
+                  "cm_penalize_known_bad", "cm_eval_indexed", "cm_sampler_create",
+                  "cm_sampler_destroy", "cm_sample_buckets"):
             getattr(L, f).restype = i32
         L.cm_last_error.restype = ctypes.c_char_p
         L.cm_last_error.argtypes = []

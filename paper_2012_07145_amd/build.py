@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cm_api.hip", "cm_step.hip", "cm_serve.hip", "k_plain.hip", "k_bf16.hip", "k_topk.hip", "k_step.hip", "k_fp8.hip", "k_freeze.hip", "k_penalty.hip"]
+SOURCES = ["cm_api.hip", "cm_step.hip", "cm_serve.hip", "k_plain.hip", "k_bf16.hip", "k_topk.hip", "k_step.hip", "k_fp8.hip", "k_freeze.hip", "k_penalty.hip", "cm_sample.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -170,3 +170,14 @@ def test_penalty_arguments_are_rejected_before_device_work(cm):
     assert L.cm_penalize_known_bad(ctypes.byref(b), buf, buf, 2, float("nan"), buf, None) == _lib.CM_EINVAL
     assert L.cm_penalize_known_bad(ctypes.byref(b), None, buf, 2, 1.0, buf, None) == _lib.CM_EINVAL
     assert L.cm_penalize_known_bad(ctypes.byref(b), None, None, 0, 1.0, None, None) == _lib.CM_OK
+
+
+def test_sampler_arguments_are_rejected_before_device_work(cm):
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.cm_sampler_create(0, 10, ctypes.byref(h)) == _lib.CM_EINVAL
+    assert L.cm_sampler_create(1, 0, ctypes.byref(h)) == _lib.CM_EINVAL
+    assert L.cm_sampler_create(1, 2 ** 31, ctypes.byref(h)) == _lib.CM_EINVAL
+    assert L.cm_sampler_destroy(None) == _lib.CM_EINVAL
+    assert L.cm_sample_buckets(None, None, None, None, None, None, None) == _lib.CM_EINVAL
