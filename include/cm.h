@@ -375,13 +375,13 @@ cm_status cm_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t *code
  * for `slots` steps that may be in flight at once.  cm_step_run writes the
  * batch's descriptors into pinned host memory; the step then runs as
  *   copy of the descriptors to the device -> hoist (only when U is NULL) ->
- *   one persistent CM_BF16 evaluation kernel whose workgroups take tasks
+ *   one persistent CM_BF16 or CM_FP8 evaluation kernel whose workgroups take tasks
  *   from a device-wide queue, with each query's top-k selection run by the
  *   workgroup that finishes the query's last task,
  * either as one graph launch (captured once per slot and configuration) or
  * as plain launches.  The launch shape depends only on the configuration,
  * never on the batch.  Results are bit-identical to cm_eval_batch /
- * cm_eval_hoisted (CM_BF16) followed by cm_topk_per_query, for every
+ * cm_eval_hoisted (same precision) followed by cm_topk_per_query, for every
  * configuration.
  * ------------------------------------------------------------------------ */
 typedef struct cm_step cm_step;
@@ -404,7 +404,9 @@ typedef struct {
 } cm_step_config;
 
 /* Create a step on the current device for `model`, which must outlive it.
- * Only CM_BF16 is supported (CM_EUNSUPPORTED otherwise).  Allocates device
+ * CM_BF16 and CM_FP8 are supported (CM_EUNSUPPORTED otherwise); CM_FP8 needs
+ * the model's FP8 form (CM_EINVAL otherwise), whose hidden scale the step's
+ * own hoist reads at run time.  Allocates device
  * memory for the descriptors, control words, hoisted rows and selection
  * lists of every slot, and pinned host memory for the descriptors.
  * Errors: CM_EINVAL, CM_EUNSUPPORTED, CM_ENOMEM, CM_EDEVICE. */
@@ -414,7 +416,7 @@ cm_status cm_step_create(const cm_model *model, cm_precision precision,
 cm_status cm_step_destroy(cm_step *step);
 
 /* One beam step of every query of `batch` (layouts as for cm_eval_batch
- * with CM_BF16; the batch's base pointers and every output pointer are
+ * with the step's precision; the batch's base pointers and every output pointer are
  * device pointers):
  *   - U: hoisted rows as cm_hoist_stages writes them for this batch, or
  *     NULL to hoist inside the step (then pipe must be given);
@@ -467,12 +469,13 @@ cm_status cm_step_kernel_time(cm_step *step, float *us);
  * micro-batches on different slots overlap on the device.  Session state
  * stays on the device: the hoisted rows of its stages (computed once, at
  * open) and its latest beam.  Every result is the same as the request
- * evaluated alone (cm_eval_batch CM_BF16 + cm_topk_per_query), bit for bit.
+ * evaluated alone (cm_eval_batch in the server's precision +
+ * cm_topk_per_query), bit for bit.
  * ------------------------------------------------------------------------ */
 typedef struct cm_server cm_server;
 
 typedef struct {
-    cm_precision precision;     /* CM_BF16 */
+    cm_precision precision;     /* CM_BF16, or CM_FP8 (model with its FP8 form) */
     int32_t k;                  /* largest beam width of a request, 1 .. CM_MAX_K */
     int64_t arena_bytes;        /* admission limit, see cm_serve_submit */
     int32_t max_slots;          /* micro-batches in flight, 1 .. 8 */
@@ -485,8 +488,8 @@ typedef struct {
 
 /* One beam step of a session: n_cands candidates over the session's stages.
  * sched and terms are device pointers owned by the caller, laid out as for
- * cm_eval_batch (bf16 bits [S][n_cands][40] and float32 [S][n_cands][8],
- * 16-byte aligned), and must stay valid and unchanged until the request's
+ * cm_eval_batch (bf16 bits or e4m3 codes [S][n_cands][40], as the server's
+ * precision, and float32 [S][n_cands][8], 16-byte aligned), and must stay valid and unchanged until the request's
  * result has been polled or the request canceled. */
 typedef struct {
     int32_t n_cands;      /* 0 .. max_batch_cands */

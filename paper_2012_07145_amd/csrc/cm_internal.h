@@ -151,7 +151,7 @@ struct TopkLaunch {
 constexpr int STEP_MAX_QUERIES = CM_STEP_MAX_QUERIES;
 
 struct StepQ {
-    const uint16_t *x;  // schedule features [S][N][40], bf16
+    const void *x;      // schedule features [S][N][40]: bf16 bits or e4m3 codes
     const float *t;     // cost terms [S][N][8]
     float *u;           // hoisted rows [S][32] (written by the hoist when it runs)
     const float *pipe;  // algorithm features [S][56] (hoist only)
@@ -194,7 +194,7 @@ constexpr int CTL_TCNT = CTL_QCNT + STEP_MAX_QUERIES;
 
 // One query of a step, as absolute device pointers (host side).
 struct StepReq {
-    const uint16_t *x;
+    const void *x;      // bf16 bits or e4m3 codes, as the step's precision
     const float *t;
     float *u;
     const float *pipe;  // needed only when the step hoists
@@ -242,10 +242,10 @@ hipError_t launch_penalty(const PenaltyLaunch &L, const uint64_t *hashes, const 
                           int64_t n_bad, float penalty, float *cost, hipStream_t st);
 hipError_t launch_topk(const TopkLaunch &L, const float *cost, uint64_t *tpart, int32_t *tcnt,
                        int32_t *idx_out, float *val_out, hipStream_t st);
-hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m, int grid,
-                             hipStream_t st);
-hipError_t launch_step_bf16(const StepHead *h, const StepQ *qs, uint32_t *ctl, uint64_t *tpart,
-                            const Model &m, int grid, hipStream_t st);
+hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m,
+                             cm_precision prec, int grid, hipStream_t st);
+hipError_t launch_step(const StepHead *h, const StepQ *qs, uint32_t *ctl, uint64_t *tpart,
+                       const Model &m, cm_precision prec, int grid, hipStream_t st);
 
 // Device side: data one workgroup hands to another inside a launch (costs
 // read by the selecting workgroup, per-tile beam lists) is stored and loaded

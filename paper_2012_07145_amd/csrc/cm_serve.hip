@@ -29,7 +29,7 @@ enum class St { Pending, Admitted, Done, Canceled, Failed };
 struct Req {
     int32_t session = -1;
     int32_t N = 0, k = 0, S = 0;
-    const uint16_t *x = nullptr;
+    const void *x = nullptr;  // bf16 bits or e4m3 codes, as the server's precision
     const float *t = nullptr;
     int64_t bytes = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -109,9 +109,12 @@ struct cm_server {
 
 namespace {
 
-int64_t request_bytes(int32_t S, int32_t N, int32_t k)
+// Feature bytes per row: bf16 bits or e4m3 codes.
+int64_t feature_bytes(cm_precision prec) { return prec == CM_FP8 ? cm::FS : cm::FS * 2; }
+
+int64_t request_bytes(cm_precision prec, int32_t S, int32_t N, int32_t k)
 {
-    return (int64_t)S * N * (cm::FS * 2 + cm::C * 4) + (int64_t)N * 4 + (int64_t)k * 8;
+    return (int64_t)S * N * (feature_bytes(prec) + cm::C * 4) + (int64_t)N * 4 + (int64_t)k * 8;
 }
 
 void free_server(cm_server *V)
@@ -160,7 +163,7 @@ void set_fault(cm_server &V, const char *what, hipError_t e)
 void retire(cm_server &V, SlotState &sl)
 {
     V.kernel_us += (double)(sl.h_clk[1] - sl.h_clk[0]) / cm::CLOCK_MHZ;
-    V.kernel_bytes += sl.rows * (cm::FS * 2 + cm::C * 4) + sl.cands * 4;
+    V.kernel_bytes += sl.rows * (feature_bytes(V.cfg.precision) + cm::C * 4) + sl.cands * 4;
     const double now = us_since(V.t0);
     for (size_t j = 0; j < sl.tickets.size(); ++j) {
         auto it = V.reqs.find(sl.tickets[j]);
@@ -309,7 +312,8 @@ void worker_main(cm_server *Vp)
 cm_status check_cfg(const cm_server_cfg *c)
 {
     if (!c) return fail(CM_EINVAL, "cfg is NULL");
-    if (c->precision != CM_BF16) return fail(CM_EUNSUPPORTED, "the server supports CM_BF16 only");
+    if (c->precision != CM_BF16 && c->precision != CM_FP8)
+        return fail(CM_EUNSUPPORTED, "the server supports CM_BF16 and CM_FP8 only");
     if (c->k < 1 || c->k > CM_MAX_K) return fail(CM_EINVAL, "k outside [1, %d]", CM_MAX_K);
     if (c->max_slots < 1 || c->max_slots > MAX_SERVER_SLOTS)
         return fail(CM_EINVAL, "max_slots outside [1, %d]", MAX_SERVER_SLOTS);
@@ -341,7 +345,7 @@ cm_status check_request(cm_server &V, int32_t sid, const cm_request *rq)
     if (sid < 0 || sid >= (int32_t)V.sessions.size() || !V.sessions[sid].used ||
         V.sessions[sid].closing)
         return fail(CM_ENOTFOUND, "no open session %d", sid);
-    const int64_t bytes = request_bytes(V.sessions[sid].S, rq->n_cands, rq->k);
+    const int64_t bytes = request_bytes(V.cfg.precision, V.sessions[sid].S, rq->n_cands, rq->k);
     if (bytes > V.cfg.arena_bytes)
         return fail(CM_E2BIG, "request needs %lld arena bytes, the arena has %lld",
                     (long long)bytes, (long long)V.cfg.arena_bytes);
@@ -357,9 +361,9 @@ uint64_t enqueue(cm_server &V, int32_t sid, const cm_request *rq)
     r.N = rq->n_cands;
     r.k = rq->k;
     r.S = V.sessions[sid].S;
-    r.x = static_cast<const uint16_t *>(rq->sched);
+    r.x = rq->sched;
     r.t = rq->terms;
-    r.bytes = request_bytes(r.S, r.N, r.k);
+    r.bytes = request_bytes(V.cfg.precision, r.S, r.N, r.k);
     r.t_submit = us_since(V.t0);
     if (V.first_submit < 0) V.first_submit = r.t_submit;
     ++V.n_sub;
@@ -409,7 +413,7 @@ cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_s
         ok = ok && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess;
         if (ok) {
             const cm_step_desc sd{c.max_batch_queries, 1, c.max_batch_cands, c.k, 1};
-            ok = cm_step_create(model, CM_BF16, &sd, &s.step) == CM_OK;
+            ok = cm_step_create(model, cfg->precision, &sd, &s.step) == CM_OK;
         }
     }
     if (!ok) {
@@ -490,7 +494,7 @@ cm_status cm_session_open(cm_server *V, const float *pipe_host, int32_t n_stages
         if (e != hipSuccess) {
             rc = fail(CM_EDEVICE, "session set-up copy failed: %s", hipGetErrorString(e));
         } else {
-            rc = cm_hoist_stages(V->model, CM_BF16, &b, session_U(*V, sid), V->setup);
+            rc = cm_hoist_stages(V->model, V->cfg.precision, &b, session_U(*V, sid), V->setup);
             if (rc == CM_OK && (e = hipStreamSynchronize(V->setup)) != hipSuccess)
                 rc = fail(CM_EDEVICE, "session set-up failed: %s", hipGetErrorString(e));
         }

@@ -34,6 +34,7 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct cm_step {
     const cm_model *model = nullptr;
+    cm_precision prec = CM_BF16;  // CM_BF16 or CM_FP8
     int device = 0;
     cm_step_desc cap{};
     cm_step_config cfg{};
@@ -196,9 +197,10 @@ hipError_t issue(const cm_step &S, Slot &sl, bool hoist, size_t bytes, hipStream
     const StepQ *qs = reinterpret_cast<const StepQ *>(sl.d_block + sizeof(StepHead));
     hipError_t e = hipMemcpyAsync(sl.d_block, sl.h_block, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    if (hoist && (e = launch_step_hoist(h, qs, S.model->m, hoist_grid(S), st)) != hipSuccess)
+    if (hoist &&
+        (e = launch_step_hoist(h, qs, S.model->m, S.prec, hoist_grid(S), st)) != hipSuccess)
         return e;
-    return launch_step_bf16(h, qs, sl.d_ctl, sl.d_tpart, S.model->m, grid_of(S), st);
+    return launch_step(h, qs, sl.d_ctl, sl.d_tpart, S.model->m, S.prec, grid_of(S), st);
 }
 
 cm_status get_exec(cm_step &S, Slot &sl, bool hoist, hipGraphExec_t *out)
@@ -270,7 +272,8 @@ void batch_requests(const cm_step &S, const cm_batch *b, const float *U, int32_t
     for (int q = 0; q < b->n_queries; ++q) {
         const cm_query &Q = b->queries[q];
         StepReq &R = r[q];
-        R.x = static_cast<const uint16_t *>(b->sched) + Q.sched_off;
+        R.x = static_cast<const unsigned char *>(b->sched) +
+              Q.sched_off * (S.prec == CM_FP8 ? 1 : 2);
         R.t = b->terms + Q.terms_off;
         R.u = ubase + urow * H;
         R.pipe = U ? nullptr : b->pipe + Q.pipe_off;
@@ -351,7 +354,10 @@ cm_status cm_step_create(const cm_model *model, cm_precision prec, const cm_step
     using namespace cm;
     if (!model || !d || !out) return fail(CM_EINVAL, "NULL argument");
     *out = nullptr;
-    if (prec != CM_BF16) return fail(CM_EUNSUPPORTED, "the step supports CM_BF16 only");
+    if (prec != CM_BF16 && prec != CM_FP8)
+        return fail(CM_EUNSUPPORTED, "the step supports CM_BF16 and CM_FP8 only");
+    if (prec == CM_FP8 && !model->m.d_fp8)
+        return fail(CM_EINVAL, "model has no FP8 form (cm_model_prepare_fp8)");
     if (d->max_queries < 1 || d->max_queries > CM_STEP_MAX_QUERIES || d->max_stages < 1 ||
         d->max_cands < 0 || d->max_k < 1 || d->max_k > CM_MAX_K || d->slots < 1 ||
         d->slots > MAX_SLOTS)
@@ -361,6 +367,7 @@ cm_status cm_step_create(const cm_model *model, cm_precision prec, const cm_step
     cm_step *S = new (std::nothrow) cm_step;
     if (!S) return fail(CM_ENOMEM, "host allocation failed");
     S->model = model;
+    S->prec = prec;
     S->cap = *d;
     S->cfg = cm_step_config{0, 1, 1};
     S->max_tiles = d->max_cands / TOPK_TILE + d->max_queries;

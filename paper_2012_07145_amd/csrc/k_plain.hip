@@ -68,11 +68,14 @@ __global__ __launch_bounds__(64) void k_hoist(EvalLaunch L, const float *__restr
 }
 
 // Hoist of a step: the rows of every query, grid-stride, from the device
-// descriptors (the bf16 evaluator's form, with W_1[:, 24:] b_s folded in).
+// descriptors (the folded form of the bf16 and FP8 evaluators, with
+// W_1[:, 24:] b_s folded in), times *scale when given (the FP8 form's s_h,
+// read at run time so that a replayed graph follows the model's form).
 __global__ __launch_bounds__(64) void k_hoist_step(const StepHead *__restrict__ h,
                                                    const StepQ *__restrict__ qs,
                                                    const float *__restrict__ params,
-                                                   const float *__restrict__ beta)
+                                                   const float *__restrict__ beta,
+                                                   const float *__restrict__ scale)
 {
     __shared__ int32_t row0[STEP_MAX_QUERIES];
     __shared__ float lp[FP];
@@ -90,7 +93,8 @@ __global__ __launch_bounds__(64) void k_hoist_step(const StepHead *__restrict__ 
         }
         const StepQ &D = qs[lo];
         const int s = r - row0[lo];
-        hoist_row(params, beta, 1, 1.f, D.pipe + (int64_t)s * FP, D.u + (int64_t)s * H, lp, ep);
+        hoist_row(params, beta, 1, scale ? *scale : 1.f, D.pipe + (int64_t)s * FP,
+                  D.u + (int64_t)s * H, lp, ep);
     }
 }
 
@@ -173,10 +177,12 @@ hipError_t launch_hoist(const EvalLaunch &L, const Model &m, bool fold, float sc
     return hipGetLastError();
 }
 
-hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m, int grid,
-                             hipStream_t st)
+hipError_t launch_step_hoist(const StepHead *h, const StepQ *qs, const Model &m,
+                             cm_precision prec, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hoist_step, dim3(grid), dim3(64), 0, st, h, qs, m.d_params, m.d_beta);
+    const float *scale = prec == CM_FP8 ? &m.d_fp8->uh : nullptr;
+    hipLaunchKernelGGL(k_hoist_step, dim3(grid), dim3(64), 0, st, h, qs, m.d_params, m.d_beta,
+                       scale);
     return hipGetLastError();
 }
 

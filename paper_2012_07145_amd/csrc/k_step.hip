@@ -1,11 +1,12 @@
-// k_step.hip -- the persistent step kernel: bf16 evaluation of many ragged
-// queries (Sec. 5.2) and each query's beam selection (Sec. 4, Sec. 4.4) in
-// one launch whose shape never depends on the batch.
+// k_step.hip -- the persistent step kernel: bf16 or FP8 evaluation of many
+// ragged queries (Sec. 5.2) and each query's beam selection (Sec. 4, Sec. 4.4)
+// in one launch whose shape never depends on the batch.
 //
 // A fixed grid of workgroups (8 waves each) takes tasks from a device-wide
 // queue (one atomic add per task, taken when the previous task ends).  A task is `gpt`
 // consecutive row-tile groups of one query, evaluated exactly as the
-// per-call kernel does (eval_bf16.h), so the costs are bit-identical to it.
+// per-call kernels do (eval_bf16.h, eval_fp8.h), so the costs are
+// bit-identical to them.
 // Tasks never straddle a selection tile of TOPK_TILE candidates; the
 // workgroup whose task completes a tile (an arrival count per tile) selects
 // that tile's k best, and for a query of several tiles the last tile to
@@ -13,6 +14,7 @@
 // still being evaluated.  All control words are left at zero when the
 // kernel ends, so the next launch needs no clearing.
 #include "eval_bf16.h"
+#include "eval_fp8.h"
 #include "topk_dev.h"
 
 namespace cm {
@@ -25,7 +27,7 @@ constexpr int NT = EVAL_WAVES * 64;
 
 // Selection of tile `tile` of query q after the last of its tasks has
 // arrived, and for a query of several tiles, the merge by the last tile.
-__device__ void select_tile(const StepQ &D, int q, int tile, int k, uint32_t *qcnt,
+__device__ __forceinline__ void select_tile(const StepQ &D, int q, int tile, int k, uint32_t *qcnt,
                             uint64_t *tpart, TopkShared<NT> &tsh, int &s_query_last)
 {
     const int tid = threadIdx.x;
@@ -51,9 +53,55 @@ __device__ void select_tile(const StepQ &D, int q, int tile, int k, uint32_t *qc
     }
 }
 
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_step_bf16(
-    const StepHead *__restrict__ h, const StepQ *__restrict__ qs, uint32_t *ctl,
-    uint64_t *tpart, const Bf16Pack *__restrict__ pk)
+// One task's evaluation: gpt row-tile groups of one query.
+__device__ __forceinline__ void eval_task(const StepQ &D, int tq, int gpt, int wave, int lane,
+                                          const Bf16Pack *__restrict__ pk, const Pairs &kp,
+                                          GroupShared &gsh)
+{
+    QueryView Q;
+    Q.x = static_cast<const uint16_t *>(D.x);
+    Q.t = D.t;
+    Q.u = D.u;
+    Q.cost = D.cost;
+    Q.S = D.S;
+    Q.N = D.N;
+    Q.P = D.parts;
+    const int group_rows = TILE_ROWS * (EVAL_WAVES / Q.P);
+    const Weights w = load_weights(pk, lane);
+    for (int g = 0; g < gpt; ++g) {
+        const int group = tq * gpt + g;
+        if (group * group_rows >= Q.N) break;  // uniform
+        eval_group<true>(Q, group, wave, lane, w, kp, gsh);
+        __syncthreads();  // the group's LDS is reused by the next group
+    }
+}
+
+__device__ __forceinline__ void eval_task(const StepQ &D, int tq, int gpt, int wave, int lane,
+                                          const Fp8Pack *__restrict__ pk, const Pairs &,
+                                          GroupShared &gsh)
+{
+    fp8eval::QueryView8 Q;
+    Q.x = static_cast<const uint8_t *>(D.x);
+    Q.t = D.t;
+    Q.u = D.u;
+    Q.cost = D.cost;
+    Q.S = D.S;
+    Q.N = D.N;
+    Q.P = D.parts;
+    const int group_rows = TILE_ROWS * (EVAL_WAVES / Q.P);
+    const fp8eval::Weights8 w = fp8eval::load_weights8(pk, lane);
+    for (int g = 0; g < gpt; ++g) {
+        const int group = tq * gpt + g;
+        if (group * group_rows >= Q.N) break;  // uniform
+        fp8eval::eval_group8<true>(Q, group, wave, lane, w, gsh);
+        __syncthreads();
+    }
+}
+
+template <class Pack>
+__device__ __forceinline__ void step_body(const StepHead *__restrict__ h,
+                                          const StepQ *__restrict__ qs, uint32_t *ctl,
+                                          uint64_t *tpart, const Pack *__restrict__ pk)
 {
     __shared__ GroupShared gsh;
     __shared__ TopkShared<NT> tsh;
@@ -85,25 +133,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         }
         const int q = __builtin_amdgcn_readfirstlane(lo);
         const StepQ &D = qs[q];
-        QueryView Q;
-        Q.x = D.x;
-        Q.t = D.t;
-        Q.u = D.u;
-        Q.cost = D.cost;
-        Q.S = D.S;
-        Q.N = D.N;
-        Q.P = D.parts;
         const int tq = t - D.task0;  // task within the query
-        const int group_rows = TILE_ROWS * (EVAL_WAVES / Q.P);
-        {
-            const Weights w = load_weights(pk, lane);
-            for (int g = 0; g < gpt; ++g) {
-                const int group = tq * gpt + g;
-                if (group * group_rows >= Q.N) break;  // uniform
-                eval_group<true>(Q, group, wave, lane, w, kp, gsh);
-                __syncthreads();  // the group's LDS is reused by the next group
-            }
-        }
+        const int group_rows = TILE_ROWS * (EVAL_WAVES / D.parts);
+        eval_task(D, tq, gpt, wave, lane, pk, kp, gsh);
         // this task's costs (coherent stores) have completed before it counts
         // itself at its selection tile; the next task is taken only now, so
         // that the queue hands work to whichever workgroup is free first
@@ -142,12 +174,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
 }
 
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_step_bf16(
+    const StepHead *__restrict__ h, const StepQ *__restrict__ qs, uint32_t *ctl,
+    uint64_t *tpart, const Bf16Pack *__restrict__ pk)
+{
+    step_body(h, qs, ctl, tpart, pk);
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_step_fp8(
+    const StepHead *__restrict__ h, const StepQ *__restrict__ qs, uint32_t *ctl,
+    uint64_t *tpart, const Fp8Pack *__restrict__ pk)
+{
+    step_body(h, qs, ctl, tpart, pk);
+}
+
 }  // namespace
 
-hipError_t launch_step_bf16(const StepHead *h, const StepQ *qs, uint32_t *ctl, uint64_t *tpart,
-                            const Model &m, int grid, hipStream_t st)
+hipError_t launch_step(const StepHead *h, const StepQ *qs, uint32_t *ctl, uint64_t *tpart,
+                       const Model &m, cm_precision prec, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_step_bf16, dim3(grid), dim3(NT), 0, st, h, qs, ctl, tpart, m.d_bf16);
+    if (prec == CM_FP8)
+        hipLaunchKernelGGL(k_step_fp8, dim3(grid), dim3(NT), 0, st, h, qs, ctl, tpart, m.d_fp8);
+    else
+        hipLaunchKernelGGL(k_step_bf16, dim3(grid), dim3(NT), 0, st, h, qs, ctl, tpart,
+                           m.d_bf16);
     return hipGetLastError();
 }
 
