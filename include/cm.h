@@ -359,7 +359,9 @@ cm_status cm_fp8_calibrate(const cm_model *model, int64_t n_rows, const float *p
                            const float *sched_rows, float *in_scale_out,
                            float *act_scale_out);
 
-/* codes[i] = e4m3(log1pf(x[i]) * in_scale) for i < n, on the device: x is
+/* codes[i] = e4m3(log1p(x[i]) * in_scale) for i < n, on the device, with
+ * log1p taken in float32 (within a few ulps; a value within that distance of
+ * an e4m3 midpoint may take the neighbouring code): x is
  * float32 (device, 16-byte aligned), codes uint8 (device, 16-byte aligned,
  * may not overlap x).  Round to nearest even, saturation at +-448, NaN (e.g.
  * x < -1) -> 0x7F.  in_scale: a positive power of two.  Asynchronous on

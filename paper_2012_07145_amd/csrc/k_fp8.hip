@@ -58,10 +58,27 @@ __device__ inline uint32_t e4m3_pair(float a, float b)
     return w;
 }
 
+// log1p(x) in float32 within a few ulps, from the hardware base-2 logarithm:
+// with u = 1 + x rounded, log(u) * x / (u - 1) cancels the rounding of u to
+// first order (Goldberg's method, "What every computer scientist should know
+// about floating-point arithmetic", 1991); u == 1 means log1p(x) = x to
+// float32 precision, and for huge |u - 1| (whose reciprocal would underflow)
+// the rounding of u no longer matters.  -1 gives -inf, below -1 NaN, +inf
+// stays +inf.
+__device__ inline float log1p_fast(float x)
+{
+    const float u = 1.f + x;
+    const float d = u - 1.f;
+    if (d == 0.f) return x;
+    const float l = __builtin_amdgcn_logf(u) * 0.6931471805599453f;
+    if (!(fabsf(d) < 0x1p100f)) return l;
+    return l * (x * __builtin_amdgcn_rcpf(d));
+}
+
 __device__ inline uint32_t encode4(float4 x, float s)
 {
-    const uint32_t lo = e4m3_pair(log1pf(x.x) * s, log1pf(x.y) * s);
-    const uint32_t hi = e4m3_pair(log1pf(x.z) * s, log1pf(x.w) * s);
+    const uint32_t lo = e4m3_pair(log1p_fast(x.x) * s, log1p_fast(x.y) * s);
+    const uint32_t hi = e4m3_pair(log1p_fast(x.z) * s, log1p_fast(x.w) * s);
     return lo | (hi << 16);
 }
 
@@ -84,7 +101,7 @@ __global__ __launch_bounds__(256) void k_fp8_encode(const float *__restrict__ x,
     }
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int64_t i = n16 * 16; i < n; ++i)
-            codes[i] = (uint8_t)(e4m3_pair(log1pf(x[i]) * s, 0.f) & 0xffu);
+            codes[i] = (uint8_t)(e4m3_pair(log1p_fast(x[i]) * s, 0.f) & 0xffu);
 }
 
 }  // namespace

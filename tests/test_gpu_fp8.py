@@ -18,8 +18,9 @@ FP8_TOL = 1e-5 covering the float32 coefficient dot product and Kahan sum.
 Since that bound is loose, the typical candidate is also held to float32
 agreement: at least NO_FLIP_SHARE of them within FP8_TOL, median <= 2e-6.
 The encoder is compared code by code with the oracle's encoder; a code may
-differ (by one step) only where log1p(x) * s_in lies within float32 rounding
-of a midpoint, since the GPU takes log1p in float32.
+differ (by one step) only where log1p(x) * s_in lies within ENC_TOL (relative)
+of a midpoint, since the GPU takes log1p in float32 from the hardware
+logarithm, within a few ulps.
 """
 import math
 
@@ -36,6 +37,7 @@ FP8_TOL = 1e-5
 ACC_TOL = 2e-3
 NO_FLIP_SHARE = 0.8
 IN_SCALE = 16.0   # log1p of the synthetic features stays below 28 = 448 / 16
+ENC_TOL = 1e-6    # the encoder's float32 log1p: a few ulps (2^-23 = 1.2e-7 each)
 
 
 @pytest.fixture(scope="module")
@@ -76,7 +78,7 @@ def test_encode_matches_oracle(cm, oracle_mod, n):
             g, w = int(got[i]), int(want[i])
             assert (g ^ w) < 0x80 and abs(g - w) == 1, (x[i], s, hex(g), hex(w))
             mid = 0.5 * (vals[g] + vals[w])
-            assert abs(v - mid) <= 4e-7 * abs(mid), (x[i], s, v, mid)
+            assert abs(v - mid) <= ENC_TOL * abs(mid), (x[i], s, v, mid)
         assert bad.size <= max(2, n // 100_000), bad.size
 
 
