@@ -39,7 +39,7 @@ BYTES_PER_ROW_BF16 = 40 * 2 + 8 * 4   # schedule features (bf16) + cost terms (f
 BYTES_PER_CAND_OUT = 4                # one float32 cost written per candidate
 K = 32
 SESSIONS = 256
-STEP_SOURCES = ("k_step.hip", "eval_bf16.h", "topk_dev.h")
+STEP_SOURCES = ("k_step.hip", "eval_bf16.h", "eval_fp8.h", "topk_dev.h", "cm_internal.h")
 
 
 def log(msg):
