@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-serve-tune", action="store_true",
+                    help="keep the default step configuration of the server")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 65,536 x 64 bf16 / fp8 comparison")
     ap.add_argument("--slots", type=int, default=3, help="serving micro-batches in flight")
@@ -174,6 +176,28 @@ def main():
     run_steps(args.warmup)
     torch.cuda.synchronize()
     log(f"warm-up done ({args.warmup} steps)")
+
+    # the server's step configuration: a short trial of a few launch shapes on
+    # this traffic (part of the warm-up, outside the timed region).  Only grids
+    # that fill every compute unit by themselves are tried: with fewer
+    # workgroups, consecutive micro-batches share the device and a launch's own
+    # duration no longer measures the kernel.
+    tune = None
+    if not args.no_serve_tune:
+        trials = []
+        for grid, gt in ((0, 1), (0, 2), (0, 4), (1024, 1), (1024, 2)):
+            srv.set_step_config(grid, gt, 1)
+            run_steps(2)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            c_, _ = run_steps(8)
+            torch.cuda.synchronize()
+            trials.append((c_ / (time.perf_counter() - ta), grid, gt))
+        best = max(trials)
+        srv.set_step_config(best[1], best[2], 1)
+        tune = {"chosen": srv.get_step_config(),
+                "trials": [{"grid": g, "group_tiles": t, "candidates_per_s": v} for v, g, t in trials]}
+        log(f"serving step configuration: {tune['chosen']}")
     srv.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -415,6 +439,10 @@ def main():
                    "input_gb": round(in_bytes / 1e9, 2), "slots": args.slots,
                    "max_batch_queries": args.max_batch_queries},
         "rows_per_s": rows / wall,
+        # algorithmic bytes of every timed launch over the timed wall time:
+        # the device-level rate, which counts the overlap of consecutive
+        # micro-batches that a launch's own duration cannot
+        "aggregate_gb_per_s": st["kernel_bytes"] / wall / 1e9,
         "latency": latency,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -424,6 +452,7 @@ def main():
         "cpu_baseline": cpu,
         "fp32_plain": fp32,
         "bf16_over_fp32_plain": None if fp32 is None else value / fp32["candidates_per_s"],
+        "serving_step_tuning": tune,
         "ragged_step": ragged,
         "precision": precision,
         "serving_top32_agreement_vs_fp64": s_hit / s_tot,

@@ -585,6 +585,13 @@ cm_status cm_server_get_stats(cm_server *server, cm_server_stats *out);
 /* Clears the counters and latencies (not the queue or arena state). */
 cm_status cm_server_reset_stats(cm_server *server);
 
+/* Launch configuration of the server's steps (every slot; see
+ * cm_step_config), for example the one cm_step_autotune or a short trial
+ * of the caller picks for its traffic.  Takes effect for micro-batches
+ * launched afterwards; results never depend on it.  Errors: CM_EINVAL. */
+cm_status cm_server_set_step_config(cm_server *server, const cm_step_config *cfg);
+cm_status cm_server_get_step_config(const cm_server *server, cm_step_config *cfg);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char *cm_last_error(void);
 /* (major << 16) | minor */

@@ -443,6 +443,15 @@ class Server:
     def reset_stats(self):
         check(lib().cm_server_reset_stats(self.handle))
 
+    def set_step_config(self, grid=0, group_tiles=1, use_graph=1):
+        c = _lib.cm_step_config(int(grid), int(group_tiles), int(use_graph))
+        check(lib().cm_server_set_step_config(self.handle, ctypes.byref(c)))
+
+    def get_step_config(self):
+        c = _lib.cm_step_config()
+        check(lib().cm_server_get_step_config(self.handle, ctypes.byref(c)))
+        return {"grid": c.grid, "group_tiles": c.group_tiles, "use_graph": c.use_graph}
+
 
 def cm_server_create(model: Model, k=32, arena_bytes=8 << 30, max_slots=2, max_pending=4096,
                      max_sessions=256, max_stages=128, max_batch_queries=64,

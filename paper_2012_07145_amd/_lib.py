@@ -35,6 +35,7 @@ EXPORTS = (
     "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
     "cm_sampler_create", "cm_sampler_destroy", "cm_sample_buckets",
+    "cm_server_set_step_config", "cm_server_get_step_config",
     "cm_last_error", "cm_version",
 )
 
@@ -164,6 +165,8 @@ def lib():
         L.cm_sampler_create.argtypes = [i32, i64, ctypes.POINTER(vp)]
         L.cm_sampler_destroy.argtypes = [vp]
         L.cm_sample_buckets.argtypes = [vp, ctypes.POINTER(cm_batch), vp, vp, vp, vp, vp]
+        L.cm_server_set_step_config.argtypes = [vp, ctypes.POINTER(cm_step_config)]
+        L.cm_server_get_step_config.argtypes = [vp, ctypes.POINTER(cm_step_config)]
         for f in ("cm_model_create", "cm_model_destroy", "cm_workspace_create",
                   "cm_workspace_destroy", "cm_eval_batch", "cm_hoist_stages",
                   "cm_eval_hoisted", "cm_topk_per_query", "cm_step_create",
@@ -175,7 +178,8 @@ def lib():
                   "cm_serve_submit_batch", "cm_serve_wait_all", "cm_model_prepare_fp8",
                   "cm_fp8_calibrate", "cm_fp8_encode", "cm_eval_stages", "cm_freeze_stages",
                   "cm_penalize_known_bad", "cm_eval_indexed", "cm_sampler_create",
-                  "cm_sampler_destroy", "cm_sample_buckets"):
+                  "cm_sampler_destroy", "cm_sample_buckets", "cm_server_set_step_config",
+                  "cm_server_get_step_config"):
             getattr(L, f).restype = i32
         L.cm_last_error.restype = ctypes.c_char_p
         L.cm_last_error.argtypes = []

@@ -725,6 +725,22 @@ cm_status cm_server_get_stats(cm_server *V, cm_server_stats *o)
     return CM_OK;
 }
 
+cm_status cm_server_set_step_config(cm_server *V, const cm_step_config *c)
+{
+    if (!V || !c) return fail(CM_EINVAL, "NULL argument");
+    for (int i = 0; i < V->cfg.max_slots; ++i) {
+        const cm_status rc = cm_step_set_config(V->slot[i].step, c);
+        if (rc != CM_OK) return rc;
+    }
+    return CM_OK;
+}
+
+cm_status cm_server_get_step_config(const cm_server *V, cm_step_config *c)
+{
+    if (!V || !c) return fail(CM_EINVAL, "NULL argument");
+    return cm_step_get_config(V->slot[0].step, c);
+}
+
 cm_status cm_server_reset_stats(cm_server *V)
 {
     if (!V) return fail(CM_EINVAL, "server is NULL");
