@@ -59,8 +59,10 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
-    ap.add_argument("--no-serve-tune", action="store_true",
-                    help="keep the default step configuration of the server")
+    ap.add_argument("--serve-tune", action="store_true",
+                    help="try a few step configurations of the server on the serving traffic "
+                         "and serve with the fastest (default: two workgroups per compute "
+                         "unit, one row-tile group per task)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 65,536 x 64 bf16 / fp8 comparison")
     ap.add_argument("--slots", type=int, default=3, help="serving micro-batches in flight")
@@ -183,7 +185,7 @@ def main():
     # workgroups, consecutive micro-batches share the device and a launch's own
     # duration no longer measures the kernel.
     tune = None
-    if not args.no_serve_tune:
+    if args.serve_tune:
         trials = []
         for grid, gt in ((0, 1), (0, 2), (0, 4), (1024, 1), (1024, 2)):
             srv.set_step_config(grid, gt, 1)
