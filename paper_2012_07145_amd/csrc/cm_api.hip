@@ -284,6 +284,14 @@ cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model 
         delete M;
         return fail(CM_EDEVICE, "copy of model parameters failed");
     }
+    // the log-transform table of the bf16 evaluator, computed by the device
+    if (cm::launch_log_table(m.d_bf16, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess) {
+        (void)hipGetLastError();
+        free_model(m);
+        delete M;
+        return fail(CM_EDEVICE, "log table of the bf16 evaluator failed");
+    }
     *out = M;
     return CM_OK;
 }

@@ -44,11 +44,22 @@ constexpr int TOPK_TILE = 4096;     // candidates per workgroup of the selection
 // bf16 split-product operands of the two dense layers, laid out as the
 // 32x32x16 bf16 matrix-core instruction reads them: 8 bf16 (16 bytes) per
 // lane per operand.  [hi/lo][k-step][lane].
+// The bf16 evaluator looks up log2(1 + x) of a feature code in a table of
+// the codes LOG_BASE .. LOG_BASE + LOG_N - 1 (x from 2^-24 to just below
+// 2^40).  Below LOG_BASE, 1 + x rounds to 1 in float32.
+constexpr uint32_t LOG_BASE = 0x3380u;
+constexpr int LOG_N = 8192;
+
 struct Bf16Pack {
     uint4 a1[2][3][64];  // folded first layer (32 hidden x 48 padded features)
     uint4 a2[2][2][64];  // coefficient layer (32 padded outputs x 32 hidden)
     float b2[8];
+    float pad[4];
+    // (high bf16 | low bf16 << 16) of log2(1 + x) for code LOG_BASE + i,
+    // filled on the device by launch_log_table
+    uint32_t logtab[LOG_N];
 };
+static_assert(offsetof(Bf16Pack, logtab) % 16 == 0, "table copied in 16-byte units");
 
 // e4m3 operands of the FP8 form, laid out as the 32x32x64 fp8 matrix core
 // reads them (32 bytes per lane and operand), and its scales.
@@ -233,6 +244,8 @@ hipError_t launch_fp8_encode(const float *x, int64_t n, float in_scale, uint8_t 
 hipError_t launch_eval_fp32(const EvalLaunch &L, const Model &m, const float *sched,
                             const float *terms, const float *U, float *cost, float *stage,
                             hipStream_t st);
+// Fill pk->logtab (the device's own arithmetic of the bf16 evaluator).
+hipError_t launch_log_table(Bf16Pack *pk, hipStream_t st);
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
                             const float *terms, const float *U, float *cost, float *stage,
                             hipStream_t st, const int32_t *ridx = nullptr, uint32_t rows = 0);

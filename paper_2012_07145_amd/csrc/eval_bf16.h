@@ -10,7 +10,9 @@
 //      80 bytes; each row is split over two lanes, 40 bytes each) and their
 //      float32 cost terms, one stage ahead of the arithmetic;
 //   2. takes log2(1 + x) in float32 (ln 2 is folded into the weights, so the
-//      layer sees log1p(x)) and splits it into high and low bf16 parts;
+//      layer sees log1p(x)) and splits it into high and low bf16 parts: by
+//      lookup in an LDS table of both parts per feature code, or, for a
+//      stage whose wave holds a code outside the table, by computing it;
 //   3. runs the first layer as D[hidden][cand] = Wf . X^T on the 32x32x16 bf16
 //      matrix core: Wf = W_1[:, 24:] W_s is the schedule embedding folded into
 //      the first layer (no activation sits between them), the accumulator
@@ -113,6 +115,77 @@ __device__ inline void log_split4(uint2 raw, bf16x8 &hi, bf16x8 &lo, const Pairs
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
+// ---- the log transform by table lookup ----
+// A bf16 feature has one of 2^16 codes, so the (high, low) bf16 parts of its
+// log2(1 + x) can be looked up instead of computed.  The table holds the codes
+// LOG_BASE .. LOG_BASE + LOG_N - 1 and is filled with log_entry, i.e. with
+// exactly the instructions of log_split, so a lookup gives the same bits.
+// A saturating subtraction maps every smaller non-negative code (1 + x == 1
+// in float32, value 0) to entry 0, which is 0.  A stage whose wave holds any
+// code above the table (features of 2^40 or more, infinities, NaNs, negative
+// values) takes log_split instead.
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Table entry of one code: (high bf16 | low bf16 << 16).
+__device__ inline uint32_t log_entry(uint32_t code, const Pairs &k)
+{
+    const float y = __builtin_amdgcn_logf(dot(code, k.one_lo, 1.0f));
+    uint32_t h, l;
+    split2(y, 0.f, h, l, k);
+    return (h & 0xffffu) | (l << 16);
+}
+
+// The two table indices of a word of two codes (saturated at 0 below the
+// table; an index of LOG_N or more is outside it).
+__device__ inline uint32_t tab_index(uint32_t w)
+{
+    const u16x2 b = {(unsigned short)LOG_BASE, (unsigned short)LOG_BASE};
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, w), b));
+}
+static_assert(LOG_N == 8192, "in-table test: bits 13..15 of each index clear");
+constexpr uint32_t TAB_OUT = 0xe000e000u;
+
+// High and low operand pairs of the two codes behind index word ix.
+__device__ inline void tab_pair(const uint32_t *tab, uint32_t ix, uint32_t &h, uint32_t &l)
+{
+    const uint32_t e0 = tab[ix & 0xffffu], e1 = tab[ix >> 16];
+    h = __builtin_amdgcn_perm(e1, e0, 0x05040100u);
+    l = __builtin_amdgcn_perm(e1, e0, 0x07060302u);
+}
+
+__device__ inline void tab_split(const uint32_t *tab, uint32_t i0, uint32_t i1, uint32_t i2,
+                                 uint32_t i3, bf16x8 &hi, bf16x8 &lo)
+{
+    uint32_t h[4], l[4];
+    tab_pair(tab, i0, h[0], l[0]);
+    tab_pair(tab, i1, h[1], l[1]);
+    tab_pair(tab, i2, h[2], l[2]);
+    tab_pair(tab, i3, h[3], l[3]);
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+__device__ inline void tab_split4(const uint32_t *tab, uint32_t i0, uint32_t i1, bf16x8 &hi,
+                                  bf16x8 &lo)
+{
+    uint32_t h[2], l[2];
+    tab_pair(tab, i0, h[0], l[0]);
+    tab_pair(tab, i1, h[1], l[1]);
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], 0u, 0u));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], 0u, 0u));
+}
+
+// Copy the table into LDS (every thread of the workgroup; the caller
+// synchronises before the first lookup).
+__device__ inline void load_table(uint32_t *tab, const Bf16Pack *__restrict__ pk)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(pk->logtab);
+    uint4 *dst = reinterpret_cast<uint4 *>(tab);
+    for (int i = threadIdx.x; i < LOG_N / 4; i += blockDim.x) dst[i] = src[i];
+}
+
 // max(x, 0) on the bit pattern (negative floats are negative integers): one
 // instruction.  It maps a NaN with the sign bit set to 0; stage_math restores
 // NaN propagation by testing one hidden pre-activation per stage, since an
@@ -191,8 +264,8 @@ __device__ inline void refill_u(float4 *ur, const float4 *ug, int s, int n, int 
 // coefficient dot product with the cost terms, and the compensated sum.
 // Returns the stage's cost (in every lane of the candidate).
 __device__ __forceinline__ float stage_math(const StageIn &in, const float4 *us, int hf,
-                                            const Weights &w, const Pairs &kp, float &sum,
-                                            float &comp)
+                                            const Weights &w, const Pairs &kp,
+                                            const uint32_t *tab, float &sum, float &comp)
 {
     // first layer: accumulator starts from U[s]; register g*4+j holds
     // hidden unit g*8 + hf*4 + j
@@ -205,16 +278,28 @@ __device__ __forceinline__ float stage_math(const StageIn &in, const float4 *us,
         acc[g * 4 + 2] = u4.z;
         acc[g * 4 + 3] = u4.w;
     }
+    // table indices of the stage's 20 codes, and whether every code of the
+    // wave is in the table (one uniform branch per stage)
+    const uint32_t ix[10] = {tab_index(in.x0.x), tab_index(in.x0.y), tab_index(in.x0.z),
+                             tab_index(in.x0.w), tab_index(in.x1.x), tab_index(in.x1.y),
+                             tab_index(in.x1.z), tab_index(in.x1.w), tab_index(in.x2.x),
+                             tab_index(in.x2.y)};
+    const uint32_t all = ix[0] | ix[1] | ix[2] | ix[3] | ix[4] | ix[5] | ix[6] | ix[7] | ix[8] |
+                         ix[9];
+    const bool fast = __builtin_amdgcn_ballot_w64((all & TAB_OUT) != 0u) == 0;
     bf16x8 bh, bl;
-    log_split(in.x0, bh, bl, kp);
+    if (fast) tab_split(tab, ix[0], ix[1], ix[2], ix[3], bh, bl);
+    else log_split(in.x0, bh, bl, kp);
     acc = mfma(w.A1h[0], bh, acc);
     acc = mfma(w.A1l[0], bh, acc);
     acc = mfma(w.A1h[0], bl, acc);
-    log_split(in.x1, bh, bl, kp);
+    if (fast) tab_split(tab, ix[4], ix[5], ix[6], ix[7], bh, bl);
+    else log_split(in.x1, bh, bl, kp);
     acc = mfma(w.A1h[1], bh, acc);
     acc = mfma(w.A1l[1], bh, acc);
     acc = mfma(w.A1h[1], bl, acc);
-    log_split4(in.x2, bh, bl, kp);
+    if (fast) tab_split4(tab, ix[8], ix[9], bh, bl);
+    else log_split4(in.x2, bh, bl, kp);
     acc = mfma(w.A1h[2], bh, acc);
     acc = mfma(w.A1l[2], bh, acc);
     acc = mfma(w.A1h[2], bl, acc);
@@ -297,7 +382,8 @@ struct GroupShared {
 // the table makes that stage's cost NaN.
 template <bool kShared, bool kStage = false, bool kIndexed = false>
 __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wave, int lane,
-                                           const Weights &w, const Pairs &kp, GroupShared &sh)
+                                           const Weights &w, const Pairs &kp,
+                                           const uint32_t *tab, GroupShared &sh)
 {
     const int P = Q.P;
     const int tile = group * (EVAL_WAVES / P) + wave / P;
@@ -369,7 +455,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             B.bad = bad;
             // keep the loads here, ahead of their use
             asm volatile("" ::: "memory");
-            const float va = stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+            const float va =
+                stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, tab, sum, comp);
             if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
             if (s + 1 >= s1) break;
 
@@ -386,7 +473,7 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             A.bad = bad;
             asm volatile("" ::: "memory");
             const float vb =
-                stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, sum, comp);
+                stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, tab, sum, comp);
             if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
         }
     }

@@ -24,6 +24,8 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     const int32_t *__restrict__ ridx, uint32_t rows)
 {
     __shared__ GroupShared sh;
+    __shared__ uint32_t tab[LOG_N];
+    load_table(tab, pk);
     const int lane = threadIdx.x & 63;
     // wave-uniform values are kept in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -43,10 +45,24 @@ __global__ __launch_bounds__(EVAL_WAVES * 64) __attribute__((amdgpu_waves_per_eu
     Q.P = E.parts;
     const Weights w = load_weights(pk, lane);
     const Pairs kp = make_pairs();
-    eval_group<false, kStage, kIndexed>(Q, blockIdx.x - E.task0, wave, lane, w, kp, sh);
+    __syncthreads();  // the table is in LDS
+    eval_group<false, kStage, kIndexed>(Q, blockIdx.x - E.task0, wave, lane, w, kp, tab, sh);
+}
+
+__global__ __launch_bounds__(256) void k_log_table(Bf16Pack *pk)
+{
+    const Pairs kp = make_pairs();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < LOG_N) pk->logtab[i] = log_entry(LOG_BASE + (uint32_t)i, kp);
 }
 
 }  // namespace
+
+hipError_t launch_log_table(Bf16Pack *pk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_log_table, dim3((LOG_N + 255) / 256), dim3(256), 0, st, pk);
+    return hipGetLastError();
+}
 
 hipError_t launch_eval_bf16(const EvalLaunch &L, const Model &m, const uint16_t *sched,
                             const float *terms, const float *U, float *cost, float *stage,

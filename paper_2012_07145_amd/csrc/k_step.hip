@@ -56,7 +56,7 @@ __device__ __forceinline__ void select_tile(const StepQ &D, int q, int tile, int
 // One task's evaluation: gpt row-tile groups of one query.
 __device__ __forceinline__ void eval_task(const StepQ &D, int tq, int gpt, int wave, int lane,
                                           const Bf16Pack *__restrict__ pk, const Pairs &kp,
-                                          GroupShared &gsh)
+                                          const uint32_t *tab, GroupShared &gsh)
 {
     QueryView Q;
     Q.x = static_cast<const uint16_t *>(D.x);
@@ -71,14 +71,14 @@ __device__ __forceinline__ void eval_task(const StepQ &D, int tq, int gpt, int w
     for (int g = 0; g < gpt; ++g) {
         const int group = tq * gpt + g;
         if (group * group_rows >= Q.N) break;  // uniform
-        eval_group<true>(Q, group, wave, lane, w, kp, gsh);
+        eval_group<true>(Q, group, wave, lane, w, kp, tab, gsh);
         __syncthreads();  // the group's LDS is reused by the next group
     }
 }
 
 __device__ __forceinline__ void eval_task(const StepQ &D, int tq, int gpt, int wave, int lane,
                                           const Fp8Pack *__restrict__ pk, const Pairs &,
-                                          GroupShared &gsh)
+                                          const uint32_t *, GroupShared &gsh)
 {
     fp8eval::QueryView8 Q;
     Q.x = static_cast<const uint8_t *>(D.x);
@@ -98,13 +98,26 @@ __device__ __forceinline__ void eval_task(const StepQ &D, int tq, int gpt, int w
     }
 }
 
+// LDS table of the log transform: the bf16 evaluator's only.
+template <class Pack> struct LogTable { static constexpr int n = 1; };
+template <> struct LogTable<Bf16Pack> { static constexpr int n = LOG_N; };
+
+// The evaluation's and the selection's LDS are never in use at the same time
+// (a workgroup-wide barrier separates every switch between them).
+union StepShared {
+    GroupShared g;
+    TopkShared<NT> t;
+};
+
 template <class Pack>
 __device__ __forceinline__ void step_body(const StepHead *__restrict__ h,
                                           const StepQ *__restrict__ qs, uint32_t *ctl,
                                           uint64_t *tpart, const Pack *__restrict__ pk)
 {
-    __shared__ GroupShared gsh;
-    __shared__ TopkShared<NT> tsh;
+    __shared__ StepShared ssh;
+    __shared__ uint32_t tab[LogTable<Pack>::n];
+    GroupShared &gsh = ssh.g;
+    TopkShared<NT> &tsh = ssh.t;
     __shared__ int32_t task0[STEP_MAX_QUERIES];
     __shared__ int s_next, s_tail, s_query_last;
     const int tid = threadIdx.x;
@@ -116,6 +129,7 @@ __device__ __forceinline__ void step_body(const StepHead *__restrict__ h,
     unsigned long long *clk = reinterpret_cast<unsigned long long *>(ctl + CTL_CLK);
 
     for (int j = tid; j < nq; j += NT) task0[j] = qs[j].task0;
+    if constexpr (LogTable<Pack>::n > 1) load_table(tab, pk);
     if (tid == 0) {
         atomicMin(&clk[0], (unsigned long long)__builtin_amdgcn_s_memrealtime());
         s_next = (int)atomicAdd(&ctl[CTL_NEXT], 1u);
@@ -135,7 +149,7 @@ __device__ __forceinline__ void step_body(const StepHead *__restrict__ h,
         const StepQ &D = qs[q];
         const int tq = t - D.task0;  // task within the query
         const int group_rows = TILE_ROWS * (EVAL_WAVES / D.parts);
-        eval_task(D, tq, gpt, wave, lane, pk, kp, gsh);
+        eval_task(D, tq, gpt, wave, lane, pk, kp, tab, gsh);
         // this task's costs (coherent stores) have completed before it counts
         // itself at its selection tile; the next task is taken only now, so
         // that the queue hands work to whichever workgroup is free first

@@ -61,6 +61,17 @@ struct TopkShared {
 
 __device__ inline uint32_t wave_count(bool p) { return (uint32_t)__popcll(__ballot(p)); }
 
+// The thread's index, opaque to the compiler: values derived from it (lane
+// masks, partner addresses of the sort) are recomputed where they are used
+// instead of being hoisted out of the persistent kernel's task loop, where
+// they would stay live through the evaluation and spill.
+__device__ inline int sel_tid()
+{
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // ---------------------------------------------------------------- sorting
 __device__ inline uint64_t shfl_xor64(uint64_t v, int mask)
 {
@@ -75,7 +86,7 @@ __device__ inline uint64_t shfl_xor64(uint64_t v, int mask)
 template <int NT>
 __device__ uint64_t block_sort1(uint64_t key, uint64_t *x)
 {
-    const int t = threadIdx.x;
+    const int t = sel_tid();
 #pragma unroll
     for (int size = 2; size <= NT; size <<= 1) {
 #pragma unroll
@@ -103,8 +114,9 @@ __device__ uint64_t block_sort1(uint64_t key, uint64_t *x)
 template <int NT>
 __device__ inline uint32_t block_sum(uint32_t wave_value, TopkShared<NT> &sh, int &buf)
 {
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh.cnt[buf][w] = wave_value;
+    const int tid = sel_tid();
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) sh.cnt[buf][w] = wave_value;
     __syncthreads();
     uint32_t tot = 0;
 #pragma unroll
@@ -129,8 +141,9 @@ __device__ uint32_t block_radix(const uint32_t (&val)[PER], const bool (&sel)[PE
         a &= (uint32_t)__shfl_xor((int)a, d);
         o |= (uint32_t)__shfl_xor((int)o, d);
     }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    const int tid = sel_tid();
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) {
         sh.red_and[w] = a;
         sh.red_or[w] = o;
     }
@@ -172,7 +185,7 @@ __device__ uint64_t block_threshold(int nf, uint32_t rank, TopkShared<NT> &sh)
     bool sel[PER], eq[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const int e = j * NT + (int)threadIdx.x;
+        const int e = j * NT + sel_tid();
         const uint64_t key = e < nf ? sh.filt[e] : SENT;
         hi[j] = (uint32_t)(key >> 32);
         lo[j] = (uint32_t)key;
@@ -198,7 +211,7 @@ __device__ int tile_select(const uint64_t (&key)[TopkShared<NT>::PER], int nvali
                            TopkShared<NT> &sh)
 {
     constexpr int PER = TopkShared<NT>::PER;
-    const int t = threadIdx.x;
+    const int t = sel_tid();
     const int lane = t & 63;
     if (t == 0) sh.nfilt = 0;
     uint64_t T = SENT - 1;  // at most k keys: all of them
@@ -266,7 +279,7 @@ __device__ int tile_select(const uint64_t (&key)[TopkShared<NT>::PER], int nvali
 template <int NT>
 __device__ inline void publish_list(const TopkShared<NT> &sh, int nbest, int k, uint64_t *dst)
 {
-    const int t = threadIdx.x;
+    const int t = sel_tid();
     if (t < k) store_shared(dst + t, t < nbest ? sh.best[t] : SENT);
     wait_stores();
 }
@@ -279,7 +292,7 @@ template <int NT>
 __device__ int merge_lists(const uint64_t *src, int ntiles, int N, int k, TopkShared<NT> &sh)
 {
     constexpr int PER = TopkShared<NT>::PER;
-    const int t = threadIdx.x;
+    const int t = sel_tid();
     const int total = ntiles * k;
     const int total_valid = (ntiles - 1) * k + min(k, N - (ntiles - 1) * TOPK_TILE);
     const int fresh = TOPK_TILE - k;
@@ -314,7 +327,7 @@ __device__ inline void tile_keys(const float *c, int N, int tile, uint64_t (&key
     nvalid = max(0, min(TOPK_TILE, N - beg));
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const int e = j * NT + (int)threadIdx.x;
+        const int e = j * NT + sel_tid();
         if (e < nvalid) {
             const float v = kShared ? load_shared(c + beg + e) : c[beg + e];
             key[j] = make_key(v, (uint32_t)(beg + e));
@@ -330,7 +343,7 @@ template <int NT, bool kShared>
 __device__ inline void write_beam(const TopkShared<NT> &sh, int nbest, int k, const float *c,
                                   int32_t *idx, float *val)
 {
-    const int t = threadIdx.x;
+    const int t = sel_tid();
     if (t < k) {
         int32_t id = -1;
         float v = __builtin_inff();

@@ -321,3 +321,39 @@ def test_bf16_long_query_reads_hoisted_rows_from_memory(cm, oracle_mod, model, p
     qq = gc.quantized(q)
     ref = oracle_mod.eval_query(params, qq.pipe, qq.sched, qq.terms)
     assert gc.rel_err(c, ref).max() <= BF16_TOL
+
+
+def test_bf16_log_table_equals_computed_log(cm, oracle_mod):
+    # The bf16 evaluator looks the log transform of a feature code up in a
+    # table unless a stage of the wave holds a code outside it (2^40 and up,
+    # infinities, NaNs, negatives); then it computes it.  Both must give the
+    # same bits.  Feature 5 walks every finite non-negative bf16 code; feature
+    # 6 has zero weight, and in the second query it is 2^50 everywhere, which
+    # sends every stage down the computed path without changing the cost.
+    from synth import bf16_bits_to_f32
+    from synth.workloads import PARAM_LAYOUT
+    params = model_params(bias=True).copy()
+    off = 0
+    for name, shape in PARAM_LAYOUT:
+        if name == "W_s":
+            ws = params[off:off + shape[0] * shape[1]].reshape(shape)
+            ws[:, 6] = 0.0
+            break
+        off += int(np.prod(shape))
+    m = cm.cm_model_create(params)
+    S, N = 8, 4096
+    q = draw_query(np.random.default_rng(62), S, N)
+    codes = (np.arange(S * N) % 0x7f80).astype(np.uint16).reshape(S, N)
+    sched = q.sched.copy()
+    sched[:, :, 5] = bf16_bits_to_f32(codes)
+    sched[:, :, 6] = 1.0
+    a = Query(q.pipe, sched, q.terms)
+    sched_b = sched.copy()
+    sched_b[:, :, 6] = 2.0 ** 50
+    b = Query(q.pipe, sched_b, q.terms)
+    (ca,), _, _ = gc.gpu_costs(cm, m, [a], "bf16")
+    (cb,), _, _ = gc.gpu_costs(cm, m, [b], "bf16")
+    m.close()
+    assert np.array_equal(ca.view(np.uint32), cb.view(np.uint32))
+    ref = oracle_mod.eval_query(params, a.pipe, gc.quantized(a).sched, a.terms)
+    assert gc.rel_err(ca, ref).max() <= BF16_TOL
