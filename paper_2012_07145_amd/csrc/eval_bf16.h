@@ -8,7 +8,11 @@
 // row tiles.  Per stage the wave
 //   1. loads the 32 candidates' bf16 schedule features (stage-major rows of
 //      80 bytes; each row is split over two lanes, 40 bytes each) and their
-//      float32 cost terms, one stage ahead of the arithmetic;
+//      float32 cost terms, one stage ahead of the arithmetic: the features
+//      as three whole-line copies from memory into the wave's LDS block
+//      (read into registers when the stage starts), the terms into
+//      registers (memoized rows, which are gathered by number, are loaded
+//      straight into registers);
 //   2. takes log2(1 + x) in float32 (ln 2 is folded into the weights, so the
 //      layer sees log1p(x)) and splits it into high and low bf16 parts: by
 //      lookup in an LDS table of both parts per feature code, or, for a
@@ -223,6 +227,14 @@ struct StageIn {
     bool bad;  // memoized rows: the stage's row number is outside the table
 };
 
+// This lane's part of a stage's hoisted row (the first layer's accumulator
+// seed): hidden units g*8 + hf*4 .. +4 for g = 0..3, from the wave's LDS slice.
+__device__ inline void read_u(float4 (&u)[4], const float4 *us, int hf)
+{
+#pragma unroll
+    for (int g = 0; g < 4; ++g) u[g] = us[g * 2 + hf];
+}
+
 // Buffer descriptor over n bytes at p (raw, untyped dword access; loads at
 // or past n bytes return 0).
 __device__ inline __amdgpu_buffer_rsrc_t buffer_over(const void *p, uint32_t n)
@@ -263,7 +275,7 @@ __device__ inline void refill_u(float4 *ur, const float4 *ug, int s, int n, int 
 // One stage of 32 candidates: both dense layers on the matrix cores, the
 // coefficient dot product with the cost terms, and the compensated sum.
 // Returns the stage's cost (in every lane of the candidate).
-__device__ __forceinline__ float stage_math(const StageIn &in, const float4 *us, int hf,
+__device__ __forceinline__ float stage_math(const StageIn &in, const float4 (&u)[4], int hf,
                                             const Weights &w, const Pairs &kp,
                                             const uint32_t *tab, float &sum, float &comp)
 {
@@ -272,7 +284,7 @@ __device__ __forceinline__ float stage_math(const StageIn &in, const float4 *us,
     f32x16 acc;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const float4 u4 = us[g * 2 + hf];
+        const float4 u4 = u[g];
         acc[g * 4 + 0] = u4.x;
         acc[g * 4 + 1] = u4.y;
         acc[g * 4 + 2] = u4.z;
@@ -370,7 +382,28 @@ struct QueryView {
 struct GroupShared {
     float2 part[EVAL_WAVES][TILE_ROWS];
     float4 u[EVAL_WAVES][USTAGE * H / 4];
+    // one stage of each wave's feature rows (32 rows x 80 bytes), copied
+    // from memory straight into LDS
+    uint4 xs[EVAL_WAVES][TILE_ROWS * FS * 2 / 16];
 };
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// The 2,560 contiguous bytes of a wave's 32 feature rows of one stage into
+// its LDS block: three 16-byte-per-lane copies that each cover whole cache
+// lines (lane l's bytes land at 16 l), so every line is requested once.  Bytes
+// past the end of the buffer read as zero.
+__device__ inline void dma_rows(uint4 *xsw, __amdgpu_buffer_rsrc_t xr, uint32_t row0, uint32_t soff,
+                                int lane)
+{
+    const uint32_t vo = row0 + (uint32_t)lane * 16;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)xsw, 16, vo, soff, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)(xsw + 64), 16, vo + 1024, soff, 0, 0);
+    if (lane < 32)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)(xsw + 128), 16, vo + 2048, soff, 0,
+                                                 0);
+}
+static_assert(TILE_ROWS * FS * 2 == 2560, "three copies of 1,024 + 1,024 + 512 bytes");
 
 // Evaluate row-tile group `group` of a query: EVAL_WAVES / P tiles of 32
 // candidates, every wave one (tile, stage part).  Every thread of the
@@ -392,8 +425,10 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     const int hf = lane >> 5;
     const int i = tile * TILE_ROWS + n;
     const bool valid = i < Q.N;
-    // rows past the end of the query read the last row instead: every load
-    // stays in bounds and the results of those rows are never stored
+    // rows past the end of the query compute on other bytes (the last row's
+    // terms, and whatever features follow the query's rows, or zeros past the
+    // buffer's end); every load stays in bounds and their results are never
+    // stored
     const int ic = valid ? i : Q.N - 1;
     // stages [s0, s1) of this part; a tile past the query's end does no work
     const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
@@ -431,7 +466,64 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     float4 *ur = sh.u[wave];
 
     float sum = 0.f, comp = 0.f;
-    if (s0 < s1) {
+    if (!kIndexed && s0 < s1) {
+        // features: copied into this wave's LDS block one stage ahead of the
+        // arithmetic and read from there into registers at the stage's start
+        // (each 80-byte row: lane n + 32 hf takes bytes 16 hf, 32 + 16 hf and
+        // 64 + 8 hf); terms: loaded into two alternating register buffers
+        uint4 *xsw = sh.xs[wave];
+        const uint32_t row0 = (uint32_t)tile * TILE_ROWS * (FS * 2);
+        const uint2 *xs2 = reinterpret_cast<const uint2 *>(xsw);
+        float4 tA, tB;
+        auto load_t = [&](float4 &t) {
+            t = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, 0));
+        };
+        auto stage_in = [&](StageIn &in, const float4 &t) {
+            in.x0 = xsw[5 * n + hf];
+            in.x1 = xsw[5 * n + 2 + hf];
+            in.x2 = xs2[10 * n + 8 + hf];
+            in.t = t;
+            in.bad = false;
+            // the rows are in registers before the block is refilled
+            asm volatile("" ::"v"(in.x0.x), "v"(in.x0.y), "v"(in.x0.z), "v"(in.x0.w),
+                         "v"(in.x1.x), "v"(in.x1.y), "v"(in.x1.z), "v"(in.x1.w), "v"(in.x2.x),
+                         "v"(in.x2.y)
+                         : "memory");
+        };
+        dma_rows(xsw, xr, row0, xsoff, lane);
+        load_t(tA);
+        for (int s = s0; s < s1; s += 2) {
+            if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
+            StageIn in;
+            float4 u[4];
+            read_u(u, ur + ((s - s0) % USTAGE) * (H / 4), hf);
+            stage_in(in, tA);
+            if (s + 1 < s1) {
+                xsoff += xstep;
+                tsoff += tstep;
+                dma_rows(xsw, xr, row0, xsoff, lane);
+                load_t(tB);
+            }
+            asm volatile("" ::: "memory");
+            const float va = stage_math(in, u, hf, w, kp, tab, sum, comp);
+            if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
+            if (s + 1 >= s1) break;
+
+            if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
+            read_u(u, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf);
+            stage_in(in, tB);
+            if (s + 2 < s1) {
+                xsoff += xstep;
+                tsoff += tstep;
+                dma_rows(xsw, xr, row0, xsoff, lane);
+                load_t(tA);
+            }
+            asm volatile("" ::: "memory");
+            const float vb = stage_math(in, u, hf, w, kp, tab, sum, comp);
+            if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
+        }
+    }
+    if (kIndexed && s0 < s1) {
         // two register buffers alternate so that a stage's loads stay in
         // flight during the previous stage's arithmetic without copies
         StageIn A, B;
@@ -455,8 +547,9 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             B.bad = bad;
             // keep the loads here, ahead of their use
             asm volatile("" ::: "memory");
-            const float va =
-                stage_math(A, ur + ((s - s0) % USTAGE) * (H / 4), hf, w, kp, tab, sum, comp);
+            float4 u[4];
+            read_u(u, ur + ((s - s0) % USTAGE) * (H / 4), hf);
+            const float va = stage_math(A, u, hf, w, kp, tab, sum, comp);
             if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
             if (s + 1 >= s1) break;
 
@@ -472,8 +565,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
             A.bad = bad;
             asm volatile("" ::: "memory");
-            const float vb =
-                stage_math(B, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf, w, kp, tab, sum, comp);
+            read_u(u, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf);
+            const float vb = stage_math(B, u, hf, w, kp, tab, sum, comp);
             if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
         }
     }
