@@ -240,10 +240,20 @@ cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model 
         for (int lane = 0; lane < 64; ++lane) {
             uint16_t hi[8], lo[8];
             for (int j = 0; j < 8; ++j) {
-                // k-slot (step st, lane half hf, element j) -> schedule feature
+                // k-slot (step st, lane half hf, element j) -> schedule feature.
+                // Step 2 holds four features per lane half: its activation
+                // operand carries their high parts in slots 0..3 and their low
+                // parts in slots 4..7, so one product with the high weights
+                // repeated in slots 4..7 takes hi*hi + hi*lo and one with the
+                // low weights (zero in 4..7) takes lo*hi.
                 const int mrow = lane & 31, hf = lane >> 5;
-                const int k = st < 2 ? st * 16 + hf * 8 + j : (j < 4 ? 32 + hf * 4 + j : -1);
-                split_bf16(k >= 0 ? Wf[mrow][k] : 0.0, hi[j], lo[j]);
+                if (st < 2) {
+                    split_bf16(Wf[mrow][st * 16 + hf * 8 + j], hi[j], lo[j]);
+                } else {
+                    uint16_t unused;
+                    split_bf16(Wf[mrow][32 + hf * 4 + (j & 3)], hi[j], j < 4 ? lo[j] : unused);
+                    if (j >= 4) lo[j] = 0;
+                }
             }
             std::memcpy(&pk.a1[0][st][lane], hi, 16);
             std::memcpy(&pk.a1[1][st][lane], lo, 16);

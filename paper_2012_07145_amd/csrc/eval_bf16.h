@@ -312,9 +312,14 @@ __device__ __forceinline__ float stage_math(const StageIn &in, const float4 (&u)
     acc = mfma(w.A1h[1], bl, acc);
     if (fast) tab_split4(tab, ix[8], ix[9], bh, bl);
     else log_split4(in.x2, bh, bl, kp);
-    acc = mfma(w.A1h[2], bh, acc);
-    acc = mfma(w.A1l[2], bh, acc);
-    acc = mfma(w.A1h[2], bl, acc);
+    // the last four features per lane half: high parts in slots 0..3, low
+    // parts in 4..7 (the packed weights repeat the high weights in 4..7)
+    {
+        const uint4 h4 = __builtin_bit_cast(uint4, bh), l4 = __builtin_bit_cast(uint4, bl);
+        const bf16x8 b2 = __builtin_bit_cast(bf16x8, make_uint4(h4.x, h4.y, l4.x, l4.y));
+        acc = mfma(w.A1h[2], b2, acc);
+        acc = mfma(w.A1l[2], b2, acc);
+    }
 
     const bool invalid = acc[0] != acc[0];  // NaN: an input outside log1p's domain
 
