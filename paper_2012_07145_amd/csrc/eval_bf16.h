@@ -393,6 +393,9 @@ struct GroupShared {
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
+// Views of a copy block in other element types (may_alias: no type-based
+// alias analysis between them and the block's own type).
+typedef uint2 __attribute__((may_alias)) lds_u2;
 
 // The 2,560 contiguous bytes of a wave's 32 feature rows of one stage into
 // its LDS block: three 16-byte-per-lane copies that each cover whole cache
@@ -478,12 +481,16 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
         // 64 + 8 hf); terms: loaded into two alternating register buffers
         uint4 *xsw = sh.xs[wave];
         const uint32_t row0 = (uint32_t)tile * TILE_ROWS * (FS * 2);
-        const uint2 *xs2 = reinterpret_cast<const uint2 *>(xsw);
+        const lds_u2 *xs2 = reinterpret_cast<const lds_u2 *>(xsw);
         float4 tA, tB;
         auto load_t = [&](float4 &t) {
             t = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, 0));
         };
         auto stage_in = [&](StageIn &in, const float4 &t) {
+            // the stage's copy (and its terms, issued before it) have landed:
+            // an explicit wait, since the compiler's own waits for copies into
+            // LDS follow its alias analysis, which need not see this read
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             in.x0 = xsw[5 * n + hf];
             in.x1 = xsw[5 * n + 2 + hf];
             in.x2 = xs2[10 * n + 8 + hf];
@@ -495,8 +502,9 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
                          "v"(in.x2.y)
                          : "memory");
         };
-        dma_rows(xsw, xr, row0, xsoff, lane);
+        // the terms go first: waiting for a stage's copy then covers them
         load_t(tA);
+        dma_rows(xsw, xr, row0, xsoff, lane);
         for (int s = s0; s < s1; s += 2) {
             if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
             StageIn in;
@@ -506,8 +514,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             if (s + 1 < s1) {
                 xsoff += xstep;
                 tsoff += tstep;
-                dma_rows(xsw, xr, row0, xsoff, lane);
                 load_t(tB);
+                dma_rows(xsw, xr, row0, xsoff, lane);
             }
             asm volatile("" ::: "memory");
             const float va = stage_math(in, u, hf, w, kp, tab, sum, comp);
@@ -520,8 +528,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             if (s + 2 < s1) {
                 xsoff += xstep;
                 tsoff += tstep;
-                dma_rows(xsw, xr, row0, xsoff, lane);
                 load_t(tA);
+                dma_rows(xsw, xr, row0, xsoff, lane);
             }
             asm volatile("" ::: "memory");
             const float vb = stage_math(in, u, hf, w, kp, tab, sum, comp);
