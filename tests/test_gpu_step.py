@@ -285,3 +285,31 @@ def test_step_errors(cm, model):
     assert e.value.status == _lib.CM_EUNSUPPORTED
     torch.cuda.synchronize()
     step.close()
+
+
+def test_step_matches_per_call_with_out_of_table_features(cm, model):
+    # Features of 2^40 and more, infinities and negative values are outside the
+    # evaluator's log table; stages of waves that hold one take the computed
+    # log transform.  The step kernel and the per-call kernels must still agree
+    # bit for bit, selection included (NaN costs sort last).
+    import torch
+    rng = np.random.default_rng(63)
+    queries = [draw_query(rng, S, N) for S, N in ((7, 300), (40, 129), (19, 1000))]
+    big = queries[0].sched.copy()
+    big[2, 17, 5] = 2.0 ** 41
+    big[5, 250, 39] = np.inf
+    queries[0] = Query(queries[0].pipe, big, queries[0].terms)
+    neg = queries[1].sched.copy()
+    neg[33, 64, 0] = -0.25
+    neg[10, 3, 12] = 3.0e38
+    queries[1] = Query(queries[1].pipe, neg, queries[1].terms)
+    k = 32
+    ref = _eager(cm, model, queries, k)
+    batch = ref[0]
+    assert not np.isfinite(ref[1][250])  # the infinite feature reaches its cost
+    step = _step_for(cm, model, queries, k)
+    cost, idx, val = _outs(batch, k)
+    cm.cm_step_run(step, batch, None, k, cost, idx, val)
+    torch.cuda.synchronize()
+    _check_against(batch, cost.cpu().numpy(), idx.cpu().numpy(), val.cpu().numpy(), ref)
+    step.close()
