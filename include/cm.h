@@ -104,8 +104,10 @@ typedef struct {
  *   W_1[32][48] b_1[32]   layer over the stacked [e_p; e_s] (e_p first), ReLU
  *   W_2[8][32]  b_2[8]    coefficient layer, ReLU -> non-negative coefficients
  * The library copies the blob to the current HIP device and derives the
- * packed forms its kernels read.  params_host is not retained.  A model is
- * immutable and may be shared by concurrent calls.
+ * packed forms its kernels read, among them a table of the bf16 evaluator's
+ * log transform, which a small kernel on the null stream fills (the call
+ * waits for it).  params_host is not retained.  A model is immutable and may
+ * be shared by concurrent calls.
  * Errors: CM_EINVAL (NULL pointer, wrong dimensions, non-finite parameter),
  * CM_ENOMEM, CM_EDEVICE. */
 cm_status cm_model_create(const cm_model_desc *desc, const float *params_host,
