@@ -49,10 +49,10 @@ struct SlotState {
     hipStream_t st = nullptr;
     cm_step *step = nullptr;
     float *d_cost = nullptr;
-    int32_t *d_idx = nullptr;
-    float *d_val = nullptr;
-    int32_t *h_idx = nullptr;  // pinned
-    float *h_val = nullptr;    // pinned
+    // the beams of a micro-batch, query j at word 2 j kb: kb indices, then
+    // kb values (one copy to the host covers the whole micro-batch)
+    uint32_t *d_beam = nullptr;
+    uint32_t *h_beam = nullptr;  // pinned
     uint64_t *h_clk = nullptr; // pinned: the step kernel's (first start, last end)
     hipEvent_t done = nullptr;
     bool busy = false;
@@ -123,10 +123,8 @@ void free_server(cm_server *V)
         if (s.step) (void)cm_step_destroy(s.step);
         if (s.st) (void)hipStreamDestroy(s.st);
         if (s.d_cost) (void)hipFree(s.d_cost);
-        if (s.d_idx) (void)hipFree(s.d_idx);
-        if (s.d_val) (void)hipFree(s.d_val);
-        if (s.h_idx) (void)hipHostFree(s.h_idx);
-        if (s.h_val) (void)hipHostFree(s.h_val);
+        if (s.d_beam) (void)hipFree(s.d_beam);
+        if (s.h_beam) (void)hipHostFree(s.h_beam);
         if (s.h_clk) (void)hipHostFree(s.h_clk);
         if (s.done) (void)hipEventDestroy(s.done);
     }
@@ -178,8 +176,11 @@ void retire(cm_server &V, SlotState &sl)
         V.arena_in_use -= r.bytes;
         --V.in_flight;
         if (r.state != St::Admitted) continue;
-        r.idx.assign(sl.h_idx + j * sl.kb, sl.h_idx + j * sl.kb + r.k);
-        r.val.assign(sl.h_val + j * sl.kb, sl.h_val + j * sl.kb + r.k);
+        const uint32_t *b = sl.h_beam + (size_t)j * 2 * sl.kb;
+        r.idx.resize(r.k);
+        r.val.resize(r.k);
+        std::memcpy(r.idx.data(), b, (size_t)r.k * 4);
+        std::memcpy(r.val.data(), b + sl.kb, (size_t)r.k * 4);
         r.t_done = now;
         r.state = St::Done;
         ++V.n_done;
@@ -234,8 +235,8 @@ bool admit(cm_server &V, SlotState &sl)
         q.u = session_U(V, r.session);
         q.pipe = nullptr;
         q.cost = sl.d_cost + off;
-        q.idx = sl.d_idx + (int64_t)j * kb;
-        q.val = sl.d_val + (int64_t)j * kb;
+        q.idx = reinterpret_cast<int32_t *>(sl.d_beam + (int64_t)j * 2 * kb);
+        q.val = reinterpret_cast<float *>(sl.d_beam + (int64_t)j * 2 * kb + kb);
         q.sidx = V.d_beam_idx + (int64_t)r.session * V.cfg.k;
         q.sval = V.d_beam_val + (int64_t)r.session * V.cfg.k;
         q.S = r.S;
@@ -256,9 +257,8 @@ bool admit(cm_server &V, SlotState &sl)
     hipError_t e = rc == CM_OK ? hipSuccess : hipErrorLaunchFailure;
     const size_t nb = take.size() * (size_t)kb;
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.h_idx, sl.d_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost, sl.st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.h_val, sl.d_val, nb * sizeof(float), hipMemcpyDeviceToHost, sl.st);
+        e = hipMemcpyAsync(sl.h_beam, sl.d_beam, 2 * nb * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           sl.st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.h_clk, cm::step_clock(sl.step), 2 * sizeof(uint64_t),
                            hipMemcpyDeviceToHost, sl.st);
@@ -405,10 +405,8 @@ cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_s
         const size_t nb = (size_t)c.max_batch_queries * c.k;
         ok = ok && hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipMalloc((void **)&s.d_cost, (size_t)c.max_batch_cands * 4) == hipSuccess;
-        ok = ok && hipMalloc((void **)&s.d_idx, nb * 4) == hipSuccess;
-        ok = ok && hipMalloc((void **)&s.d_val, nb * 4) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&s.h_idx, nb * 4, 0) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&s.h_val, nb * 4, 0) == hipSuccess;
+        ok = ok && hipMalloc((void **)&s.d_beam, 2 * nb * 4) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&s.h_beam, 2 * nb * 4, 0) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&s.h_clk, 16, 0) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess;
         if (ok) {
