@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 65,536 x 64 bf16 / fp8 comparison")
     ap.add_argument("--slots", type=int, default=3, help="serving micro-batches in flight")
+    ap.add_argument("--serve-graph", type=int, choices=(0, 1), default=None,
+                    help="server steps as a replayed HIP graph (1) or plain launches (0); "
+                         "default: the library's")
     ap.add_argument("--max-batch-queries", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
@@ -149,6 +152,8 @@ def main():
     srv = cm.cm_server_create(model, k=K, arena_bytes=16 << 30, max_slots=args.slots,
                               max_pending=8192, max_sessions=SESSIONS, max_stages=128,
                               max_batch_queries=args.max_batch_queries, max_batch_cands=1 << 20)
+    if args.serve_graph is not None:
+        srv.set_step_config(0, 1, args.serve_graph)
     sids = [srv.session_open(pipe) for _, pipe, _ in sess_in]
 
     # a step's request j of every session, as pre-marshalled arrays
@@ -188,7 +193,7 @@ def main():
     if args.serve_tune:
         trials = []
         for grid, gt in ((0, 1), (0, 2), (0, 4), (1024, 1), (1024, 2)):
-            srv.set_step_config(grid, gt, 1)
+            srv.set_step_config(grid, gt, 0)
             run_steps(2)
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -196,7 +201,7 @@ def main():
             torch.cuda.synchronize()
             trials.append((c_ / (time.perf_counter() - ta), grid, gt))
         best = max(trials)
-        srv.set_step_config(best[1], best[2], 1)
+        srv.set_step_config(best[1], best[2], 0)
         tune = {"chosen": srv.get_step_config(),
                 "trials": [{"grid": g, "group_tiles": t, "candidates_per_s": v} for v, g, t in trials]}
         log(f"serving step configuration: {tune['chosen']}")
