@@ -193,7 +193,7 @@ def main():
     if args.serve_tune:
         trials = []
         for grid, gt in ((0, 1), (0, 2), (0, 4), (1024, 1), (1024, 2)):
-            srv.set_step_config(grid, gt, 0)
+            srv.set_step_config(grid, gt, 1)
             run_steps(2)
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -201,7 +201,7 @@ def main():
             torch.cuda.synchronize()
             trials.append((c_ / (time.perf_counter() - ta), grid, gt))
         best = max(trials)
-        srv.set_step_config(best[1], best[2], 0)
+        srv.set_step_config(best[1], best[2], 1)
         tune = {"chosen": srv.get_step_config(),
                 "trials": [{"grid": g, "group_tiles": t, "candidates_per_s": v} for v, g, t in trials]}
         log(f"serving step configuration: {tune['chosen']}")

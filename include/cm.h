@@ -590,9 +590,9 @@ cm_status cm_server_reset_stats(cm_server *server);
 /* Launch configuration of the server's steps (every slot; see
  * cm_step_config), for example the one cm_step_autotune or a short trial
  * of the caller picks for its traffic.  The default is {grid 0 (two
- * workgroups per compute unit), group_tiles 1, use_graph 0}: plain launches,
- * whose lower per-launch cost shortens a lone request's latency.  Takes
- * effect for micro-batches launched afterwards; results never depend on it.
+ * workgroups per compute unit), group_tiles 1, use_graph 1}; plain launches
+ * (use_graph 0) cost a lone request less time per micro-batch.  Takes effect
+ * for micro-batches launched afterwards; results never depend on it.
  * Errors: CM_EINVAL. */
 cm_status cm_server_set_step_config(cm_server *server, const cm_step_config *cfg);
 cm_status cm_server_get_step_config(const cm_server *server, cm_step_config *cfg);

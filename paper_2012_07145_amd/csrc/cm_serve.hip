@@ -412,11 +412,6 @@ cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_s
         if (ok) {
             const cm_step_desc sd{c.max_batch_queries, 1, c.max_batch_cands, c.k, 1};
             ok = cm_step_create(model, cfg->precision, &sd, &s.step) == CM_OK;
-            // micro-batches as plain launches: a graph replay costs more host
-            // and device time than the two launches it holds, which a lone
-            // request waits for
-            const cm_step_config plain{0, 1, 0};
-            ok = ok && cm_step_set_config(s.step, &plain) == CM_OK;
         }
     }
     if (!ok) {
