@@ -181,3 +181,20 @@ def test_sampler_arguments_are_rejected_before_device_work(cm):
     assert L.cm_sampler_create(1, 2 ** 31, ctypes.byref(h)) == _lib.CM_EINVAL
     assert L.cm_sampler_destroy(None) == _lib.CM_EINVAL
     assert L.cm_sample_buckets(None, None, None, None, None, None, None) == _lib.CM_EINVAL
+
+
+def test_log_table_range_reading():
+    # The bf16 evaluator's log table holds the codes 0x3380 .. 0x3380 + 8191
+    # (csrc/cm_internal.h: LOG_BASE, LOG_N).  Every smaller non-negative code
+    # maps to entry 0, which is right only if 1 + x rounds to 1 in float32
+    # for all of them (round to nearest even), and the first code of the
+    # table must be the last one that does.  The table ends just below 2^40.
+    import numpy as np
+    from synth import bf16_bits_to_f32
+    base, n = 0x3380, 8192
+    one = np.float32(1.0)
+    below = bf16_bits_to_f32(np.arange(0, base + 1, dtype=np.uint16))
+    assert np.all(one + below == one)
+    assert one + bf16_bits_to_f32(np.array([base + 1], np.uint16))[0] > one
+    last = bf16_bits_to_f32(np.array([base + n - 1, base + n], np.uint16))
+    assert last[0] < 2.0 ** 40 <= last[1]
