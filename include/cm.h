@@ -175,9 +175,16 @@ typedef struct {
  * cost_out is a device pointer; results land at cost_out[cost_off + i].
  * Asynchronous on `stream`; allocates nothing.
  * CM_FP8 evaluates the FP8 form described below (cm_model_prepare_fp8).
+ * Size limit of CM_BF16 and CM_FP8: their kernels address one query's
+ * features and terms with 32-bit byte offsets, so each query's
+ * n_stages * n_cands * 80 (CM_BF16) or * 40 (CM_FP8) feature bytes and
+ * n_stages * n_cands * 32 term bytes must stay at or below 2^32 - 2^16;
+ * CM_FP32 has no such limit.  The descriptors are checked before the model
+ * or workspace is read.
  * Errors: CM_EINVAL (bad descriptor, misaligned offset, NULL pointer, CM_FP8
- * on a model without an FP8 form), CM_E2BIG (batch exceeds the workspace),
- * CM_EUNSUPPORTED (precision), CM_EDEVICE (launch failure). */
+ * on a model without an FP8 form), CM_E2BIG (batch exceeds the workspace, or
+ * a query exceeds the size limit), CM_EUNSUPPORTED (precision), CM_EDEVICE
+ * (launch failure). */
 cm_status cm_eval_batch(const cm_model *model, cm_precision precision,
                         const cm_batch *batch, cm_workspace *ws, float *cost_out,
                         cm_stream stream);
@@ -235,7 +242,8 @@ cm_status cm_sample_buckets(cm_sampler *sampler, const cm_batch *batch, const ui
  * that are always recomputed).  Results are bit-identical to cm_eval_batch
  * on the materialized rows.  A row number outside [0, table_rows) gives that
  * candidate a NaN cost (the table is never read outside its bounds).
- * table_rows * row bytes must stay below 4 GiB.  CM_FP32 is not supported.
+ * table_rows * row bytes must stay below 4 GiB; the size limit of
+ * cm_eval_batch applies to the terms only.  CM_FP32 is not supported.
  * Errors: as cm_eval_batch, CM_EINVAL (table_rows, row_idx),
  * CM_EUNSUPPORTED (CM_FP32). */
 cm_status cm_eval_indexed(const cm_model *model, cm_precision precision,
@@ -430,8 +438,8 @@ cm_status cm_step_destroy(cm_step *step);
  * Asynchronous on `stream`.  The call waits on the host only when the slot
  * it reuses is still in flight (more than `slots` steps queued).  Calls on
  * one step are serialised; steps in flight on different streams use
- * different slots.  Errors: CM_EINVAL, CM_E2BIG (capacity),
- * CM_EDEVICE. */
+ * different slots.  Errors: CM_EINVAL, CM_E2BIG (capacity, or a query above
+ * cm_eval_batch's size limit), CM_EDEVICE. */
 cm_status cm_step_run(cm_step *step, const cm_batch *batch, const float *U, int32_t k,
                       float *cost_out, int32_t *idx_out, float *val_out, cm_stream stream);
 
@@ -558,8 +566,9 @@ cm_status cm_session_beam(cm_server *server, int32_t session, int32_t k, int32_t
 /* Queue a request; returns at once with a ticket.  A request takes
  * n_stages * n_cands * (80 + 32) + n_cands * 4 + k * 8 bytes of the arena
  * while admitted.  Errors: CM_EINVAL, CM_ENOTFOUND (session), CM_E2BIG (can
- * never be admitted: larger than the arena or a micro-batch), CM_EAGAIN
- * (queue full), CM_EDEVICE (the server has failed). */
+ * never be admitted: larger than the arena or a micro-batch, or above
+ * cm_eval_batch's size limit for one query), CM_EAGAIN (queue full),
+ * CM_EDEVICE (the server has failed). */
 cm_status cm_serve_submit(cm_server *server, int32_t session, const cm_request *req,
                           uint64_t *ticket);
 /* Non-blocking: CM_OK with the result (the ticket is then released),

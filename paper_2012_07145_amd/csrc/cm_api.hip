@@ -32,6 +32,26 @@ cm_status fail(cm_status st, const char *fmt, ...)
     return st;
 }
 
+cm_status check_query_bytes(int64_t q, int64_t S, int64_t N, cm_precision prec, bool table)
+{
+    if (prec == CM_FP32) return CM_OK;
+    const int64_t rows = S * N;  // S, N < 2^31: no overflow
+    const int64_t fb = prec == CM_FP8 ? FS : 2 * FS;
+    if (!table && rows * fb > MAX_QUERY_BYTES)
+        return fail(CM_E2BIG,
+                    "query %lld: %lld x %lld rows of schedule features are %lld bytes, above "
+                    "the evaluator's %lld per query",
+                    (long long)q, (long long)S, (long long)N, (long long)(rows * fb),
+                    (long long)MAX_QUERY_BYTES);
+    if (rows * C * 4 > MAX_QUERY_BYTES)
+        return fail(CM_E2BIG,
+                    "query %lld: %lld x %lld rows of cost terms are %lld bytes, above the "
+                    "evaluator's %lld per query",
+                    (long long)q, (long long)S, (long long)N, (long long)(rows * C * 4),
+                    (long long)MAX_QUERY_BYTES);
+    return CM_OK;
+}
+
 }  // namespace cm
 
 namespace {
@@ -144,16 +164,14 @@ cm_status check_device(int want)
     return CM_OK;
 }
 
-// Validate a batch against a workspace.  Fills the totals.
-cm_status check_batch(const cm_batch *b, const cm::Workspace &w, cm_precision prec, bool eval)
+// Validate a batch's descriptors (no object is read): counts, offsets,
+// alignment and, for an evaluation, the per-query byte limit of the
+// precision's evaluator (table: features come from a row table).
+cm_status check_shape(const cm_batch *b, cm_precision prec, bool eval, bool table = false)
 {
     if (!b) return fail(CM_EINVAL, "batch is NULL");
     if (b->n_queries < 0) return fail(CM_EINVAL, "n_queries < 0");
     if (b->n_queries > 0 && !b->queries) return fail(CM_EINVAL, "queries is NULL");
-    if (b->n_queries > w.cap.max_queries)
-        return fail(CM_E2BIG, "batch has %d queries, workspace holds %d", b->n_queries,
-                    w.cap.max_queries);
-    int64_t stages = 0, cands = 0, rows = 0;
     for (int32_t q = 0; q < b->n_queries; ++q) {
         const cm_query &Q = b->queries[q];
         if (Q.n_stages < 1) return fail(CM_EINVAL, "query %d: n_stages %d < 1", q, Q.n_stages);
@@ -166,6 +184,23 @@ cm_status check_batch(const cm_batch *b, const cm::Workspace &w, cm_precision pr
         if (eval && (Q.terms_off % 4) != 0)
             return fail(CM_EINVAL, "query %d: terms_off %lld is not a multiple of 4", q,
                         (long long)Q.terms_off);
+        if (eval) {
+            const cm_status st = cm::check_query_bytes(q, Q.n_stages, Q.n_cands, prec, table);
+            if (st != CM_OK) return st;
+        }
+    }
+    return CM_OK;
+}
+
+// Validate a batch (already shape-checked) against a workspace's capacities.
+cm_status check_batch(const cm_batch *b, const cm::Workspace &w, bool eval)
+{
+    if (b->n_queries > w.cap.max_queries)
+        return fail(CM_E2BIG, "batch has %d queries, workspace holds %d", b->n_queries,
+                    w.cap.max_queries);
+    int64_t stages = 0, cands = 0, rows = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) {
+        const cm_query &Q = b->queries[q];
         stages += Q.n_stages;
         cands += Q.n_cands;
         rows += (int64_t)Q.n_stages * Q.n_cands;
@@ -187,7 +222,6 @@ cm_status check_batch(const cm_batch *b, const cm::Workspace &w, cm_precision pr
         if (!aligned(b->sched, 16) || !aligned(b->terms, 16) || !aligned(b->pipe, 4))
             return fail(CM_EINVAL, "sched and terms must be 16-byte aligned");
     }
-    (void)prec;
     return CM_OK;
 }
 
@@ -478,15 +512,18 @@ cm_status eval_impl(const cm_model *M, cm_precision prec, const cm_batch *b, con
 }
 
 cm_status check_eval(const cm_model *M, cm_precision prec, const cm_batch *b,
-                     const cm_workspace *W, const float *cost_out, int64_t *cands)
+                     const cm_workspace *W, const float *cost_out, int64_t *cands,
+                     bool table = false)
 {
     if (!M || !W) return fail(CM_EINVAL, "model or workspace is NULL");
     if (prec != CM_FP32 && prec != CM_BF16 && prec != CM_FP8)
         return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
+    // the descriptors first: no object is read before they have been checked
+    cm_status st = check_shape(b, prec, true, table);
+    if (st != CM_OK) return st;
     if (prec == CM_FP8 && !M->m.d_fp8)
         return fail(CM_EINVAL, "model has no FP8 form (cm_model_prepare_fp8)");
-    cm_status st = check_batch(b, W->w, prec, true);
-    if (st != CM_OK) return st;
+    if ((st = check_batch(b, W->w, true)) != CM_OK) return st;
     if ((st = check_device(M->m.device)) != CM_OK) return st;
     if (W->w.device != M->m.device) return fail(CM_EINVAL, "model and workspace devices differ");
     *cands = 0;
@@ -565,7 +602,7 @@ cm_status cm_eval_indexed(const cm_model *M, cm_precision prec, const cm_batch *
     if (prec == CM_FP32)
         return fail(CM_EUNSUPPORTED, "memoized rows need CM_BF16 or CM_FP8");
     int64_t cands = 0;
-    cm_status st = check_eval(M, prec, b, W, cost_out, &cands);
+    cm_status st = check_eval(M, prec, b, W, cost_out, &cands, true);
     if (st != CM_OK) return st;
     if (cands == 0) return CM_OK;
     const int64_t row_bytes = prec == CM_FP8 ? FS : FS * 2;
@@ -671,8 +708,9 @@ cm_status cm_topk_per_query(const float *cost, const cm_batch *b, int32_t k, cm_
     if (!W) return fail(CM_EINVAL, "workspace is NULL");
     if (k < 1 || k > CM_MAX_K || k > W->w.cap.max_k)
         return fail(CM_EINVAL, "k=%d outside [1, %d]", k, std::min(CM_MAX_K, W->w.cap.max_k));
-    cm_status st = check_batch(b, W->w, CM_FP32, false);
+    cm_status st = check_shape(b, CM_FP32, false);
     if (st != CM_OK) return st;
+    if ((st = check_batch(b, W->w, false)) != CM_OK) return st;
     if ((st = check_device(W->w.device)) != CM_OK) return st;
     if (b->n_queries == 0) return CM_OK;
     if (!idx_out || !val_out) return fail(CM_EINVAL, "idx_out or val_out is NULL");

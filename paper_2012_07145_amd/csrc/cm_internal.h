@@ -286,6 +286,18 @@ __device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "me
 // Host side: record a thread-local error message and return `st`.
 cm_status fail(cm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
+// The bf16 and FP8 evaluators address one query's schedule features and
+// cost terms through buffer resources with 32-bit byte offsets.  A query
+// whose features (S * N * 80 bytes in bf16, S * N * 40 in FP8) or terms
+// (S * N * 32 bytes) would reach this size is rejected on the host; the
+// margin covers the last row tile's reads past the query's end.
+constexpr int64_t MAX_QUERY_BYTES = ((int64_t)1 << 32) - ((int64_t)1 << 16);
+// CM_E2BIG (with a message naming query q) unless a query of S stages and N
+// candidates fits those offsets in `prec`; CM_FP32 addresses with 64-bit
+// offsets and always fits.  table: the features come from a row table
+// (memoized rows, checked against its own size), so only the terms count.
+cm_status check_query_bytes(int64_t q, int64_t S, int64_t N, cm_precision prec, bool table);
+
 #define CM_HIP(expr)                                                                     \
     do {                                                                                 \
         hipError_t e_ = (expr);                                                          \

@@ -345,6 +345,9 @@ cm_status check_request(cm_server &V, int32_t sid, const cm_request *rq)
     if (sid < 0 || sid >= (int32_t)V.sessions.size() || !V.sessions[sid].used ||
         V.sessions[sid].closing)
         return fail(CM_ENOTFOUND, "no open session %d", sid);
+    const cm_status st =
+        cm::check_query_bytes(0, V.sessions[sid].S, rq->n_cands, V.cfg.precision, false);
+    if (st != CM_OK) return st;
     const int64_t bytes = request_bytes(V.cfg.precision, V.sessions[sid].S, rq->n_cands, rq->k);
     if (bytes > V.cfg.arena_bytes)
         return fail(CM_E2BIG, "request needs %lld arena bytes, the arena has %lld",

@@ -106,6 +106,8 @@ cm_status check_step_batch(const cm_step &S, const cm_batch *b, const float *U, 
         if (Q.terms_off % 4 != 0)
             return fail(CM_EINVAL, "query %d: terms_off %lld is not a multiple of 4", q,
                         (long long)Q.terms_off);
+        const cm_status st = cm::check_query_bytes(q, Q.n_stages, Q.n_cands, S.prec, false);
+        if (st != CM_OK) return st;
         stages += Q.n_stages;
         cands += Q.n_cands;
     }

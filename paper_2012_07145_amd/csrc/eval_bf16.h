@@ -443,8 +443,9 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
 
     // byte offsets: stage rows are N * 80 (features) and N * 32 (terms) apart;
-    // a query's arrays stay below 4 GB (S <= 2^16 stages of N <= 2^16 rows is
-    // far beyond any workload; the host rejects larger)
+    // the host rejects a query whose features or terms reach MAX_QUERY_BYTES
+    // (check_query_bytes), so these 32-bit offsets, the last tile's reads
+    // past the end included, never wrap
     const uint32_t xstep = kIndexed ? 0u : (uint32_t)Q.N * FS * 2;
     const uint32_t tstep = (uint32_t)Q.N * C * 4;
     // memoized rows: the table's rows * 80 bytes fit in 32 bits (host check)

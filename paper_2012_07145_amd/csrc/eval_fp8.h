@@ -165,6 +165,8 @@ __device__ __forceinline__ void eval_group8(const QueryView8 &Q, int group, int 
     const int s0 = tile * TILE_ROWS < Q.N ? (Q.S * part) / P : 0;
     const int s1 = tile * TILE_ROWS < Q.N ? (Q.S * (part + 1)) / P : 0;
 
+    // 32-bit byte offsets: the host keeps a query's codes and terms below
+    // MAX_QUERY_BYTES (check_query_bytes)
     const uint32_t xstep = kIndexed ? 0u : (uint32_t)Q.N * FS;
     const uint32_t tstep = (uint32_t)Q.N * C * 4;
     const uint32_t xbytes = kIndexed ? Q.rows * FS : xstep * (uint32_t)Q.S;

@@ -198,3 +198,42 @@ def test_log_table_range_reading():
     assert one + bf16_bits_to_f32(np.array([base + 1], np.uint16))[0] > one
     last = bf16_bits_to_f32(np.array([base + n - 1, base + n], np.uint16))
     assert last[0] < 2.0 ** 40 <= last[1]
+
+
+def test_query_above_the_32_bit_offsets_is_rejected_before_device_work(cm):
+    # The bf16 and FP8 evaluators address one query's features and terms
+    # with 32-bit byte offsets; a query that would reach 2^32 - 2^16 bytes is
+    # rejected with CM_E2BIG before the model or workspace is read (fake
+    # handles: reading them would crash this process).
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    fake = ctypes.c_void_p(16)
+    limit = 2 ** 32 - 2 ** 16
+    buf = (ctypes.c_float * 64)()
+    base = (ctypes.addressof(buf) + 15) // 16 * 16
+
+    def batch(S, N):
+        q = (_lib.cm_query * 2)(_lib.cm_query(4, 100, 0, 0, 0, 0), _lib.cm_query(S, N, 0, 0, 0, 0))
+        return q, _lib.cm_batch(2, q, base, base, base)
+
+    # bf16: 64 x 840,000 rows of 80 feature bytes = 4.3e9
+    q, b = batch(64, 840_000)
+    assert 64 * 840_000 * 80 > limit
+    assert L.cm_eval_batch(fake, _lib.CM_BF16, ctypes.byref(b), fake, base, None) == _lib.CM_E2BIG
+    msg = L.cm_last_error()
+    assert b"query 1" in msg and b"schedule features" in msg
+    assert L.cm_eval_stages(fake, _lib.CM_BF16, ctypes.byref(b), fake, base, base, None) == _lib.CM_E2BIG
+    assert L.cm_eval_hoisted(fake, _lib.CM_BF16, ctypes.byref(b), base, fake, base, None) == _lib.CM_E2BIG
+    # the largest bf16 query below the limit is only a little smaller
+    S, N = 64, limit // (64 * 80)
+    assert S * N * 80 <= limit < S * (N + 1) * 80
+    # FP8: 40 feature bytes per row, so twice the rows before the limit
+    q, b = batch(128, 840_000)
+    assert L.cm_eval_batch(fake, _lib.CM_FP8, ctypes.byref(b), fake, base, None) == _lib.CM_E2BIG
+    assert b"schedule features" in L.cm_last_error()
+    # memoized rows: the features come from the table, the terms still count
+    # (1024 x 140,000 rows of 32 term bytes = 4.6e9)
+    q, b = batch(1024, 140_000)
+    rc = L.cm_eval_indexed(fake, _lib.CM_BF16, ctypes.byref(b), base, 16, fake, base, None)
+    assert rc == _lib.CM_E2BIG
+    assert b"cost terms" in L.cm_last_error()
