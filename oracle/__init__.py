@@ -47,7 +47,7 @@ class Oracle:
                                    ctypes.c_int32, _f32p,
                                    np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"),
                                    _f32p, _f64p, ctypes.c_double, ctypes.c_void_p,
-                                   ctypes.c_int32]
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
         L.cmo_fp8_codes.restype = None
         L.cmo_fp8_codes.argtypes = [_f32p, ctypes.c_int64, ctypes.c_double,
                                     np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
@@ -115,22 +115,29 @@ class Oracle:
         return out
 
     def eval_query_fp8(self, params, in_scale, act_scale, pipe, codes, terms, *,
-                       nthreads: int = 0, acc_tol=None):
+                       nthreads: int = 0, acc_tol=None, stage_costs: bool = False):
         """FP64 predicted runtime of the FP8 form: codes[S][N][40] uint8 are e4m3
         codes of log1p(x) * in_scale.  With acc_tol also returns each
         candidate's error bound for product sums off by acc_tol of their
-        largest term."""
+        largest term.  With stage_costs also returns the per-stage costs
+        [S][N] (and, with acc_tol, each stage's share of the bound [S][N]).
+        Returns cost, or a tuple (cost, [bound,] [stage, [stage_bound]])."""
         params, pipe, terms = _f32(params), _f32(pipe), _f32(terms)
         codes = np.ascontiguousarray(codes, dtype=np.uint8)
         S, N = codes.shape[0], codes.shape[1]
         assert codes.shape == (S, N, 40) and pipe.shape == (S, 56) and terms.shape == (S, N, 8)
         cost = np.empty(N, np.float64)
         bound = np.empty(N, np.float64) if acc_tol is not None else None
+        stage = np.empty((S, N), np.float64) if stage_costs else None
+        sbound = np.empty((S, N), np.float64) if stage_costs and acc_tol is not None else None
+
+        def vp(a):
+            return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         self.L.cmo_eval_fp8(params, float(in_scale), float(act_scale), S, N, pipe, codes,
-                            terms, cost, float(acc_tol or 0.0),
-                            None if bound is None else bound.ctypes.data_as(ctypes.c_void_p),
-                            int(nthreads))
-        return (cost, bound) if bound is not None else cost
+                            terms, cost, float(acc_tol or 0.0), vp(bound), int(nthreads),
+                            vp(stage), vp(sbound))
+        out = [cost] + [a for a in (bound, stage, sbound) if a is not None]
+        return tuple(out) if len(out) > 1 else cost
 
     def freeze(self, stage_cost):
         """Freeze flags (uint8[S]) of one candidate's per-stage costs."""

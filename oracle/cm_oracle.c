@@ -230,8 +230,10 @@ static double rounding_swing(double x, double e)
 
 void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
                   int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
-                  double *cost_out, double acc_tol, double *bound_out, int32_t nthreads)
+                  double *cost_out, double acc_tol, double *bound_out, int32_t nthreads,
+                  double *stage_cost_out, double *stage_bound_out)
 {
+    const int want_bound = bound_out != NULL || stage_bound_out != NULL;
     cmo_params P = split_params(params);
     /* folded first layer over the schedule features and its bias share */
     double Wf[H][FS], beta[H], Wq1[H][FS], Wq2[C][H];
@@ -310,7 +312,7 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
                 const double pre = a / s1;
                 const double x = (pre < 0.0 ? 0.0 : pre) * act_scale; /* ReLU, scale */
                 hq[h] = q8(x);
-                if (bound_out) {
+                if (want_bound) {
                     /* a product sum off by acc_tol of its largest term, the
                      * hoisted row off by 1e-5 of its terms' magnitudes */
                     const double e =
@@ -318,20 +320,24 @@ void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_
                     swing[h] = isnan(x) ? 0.0 : rounding_swing(x, e);
                 }
             }
-            double v = 0.0;
+            double v = 0.0, sbound = 0.0;
             for (int c = 0; c < C; ++c) {
                 double a = 0.0, pmax = 0.0, flips = 0.0;
                 for (int h = 0; h < H; ++h) {
                     a += Wq2[c][h] * hq[h];
                     if (fabs(Wq2[c][h] * hq[h]) > pmax) pmax = fabs(Wq2[c][h] * hq[h]);
-                    if (bound_out) flips += fabs(Wq2[c][h]) * swing[h];
+                    if (want_bound) flips += fabs(Wq2[c][h]) * swing[h];
                 }
                 a = a / s2 + (double)P.b2[c];
                 v += (a < 0.0 ? 0.0 : a) * (double)terms[row * C + c];
                 /* ReLU moves its output by at most its input's change */
-                if (bound_out)
-                    bound += (flips + acc_tol * pmax) / s2 * fabs((double)terms[row * C + c]);
+                if (want_bound)
+                    sbound += (flips + acc_tol * pmax) / s2 * fabs((double)terms[row * C + c]);
             }
+            /* the stage's predicted cost (Sec. 5.2) and its share of the bound */
+            if (stage_cost_out != NULL) stage_cost_out[row] = v;
+            if (stage_bound_out != NULL) stage_bound_out[row] = sbound;
+            bound += sbound;
             stage_sum += v;
         }
         cost_out[i] = stage_sum;

@@ -44,10 +44,14 @@ void cmo_fp8_codes(const float *x, int64_t n, double in_scale, uint8_t *out);
  * by acc_tol times its largest product and every hoisted row by 1e-5 of the
  * magnitudes of its terms: the hidden values whose rounding may then change
  * contribute their possible e4m3 swing through |W_2|, and each coefficient
- * its own error, times |terms|. */
+ * its own error, times |terms|.
+ * stage_cost_out[S][N] and stage_bound_out[S][N] (optional, may be NULL):
+ * every stage's predicted cost (the terms Sec. 5.2 sums over stages) and that
+ * stage's share of the bound (the shares add up to bound_out). */
 void cmo_eval_fp8(const float *params, double in_scale, double act_scale, int32_t S,
                   int32_t N, const float *pipe, const uint8_t *codes, const float *terms,
-                  double *cost_out, double acc_tol, double *bound_out, int32_t nthreads);
+                  double *cost_out, double acc_tol, double *bound_out, int32_t nthreads,
+                  double *stage_cost_out, double *stage_bound_out);
 
 /* The k best candidates: ascending cost, ties by lower index, -0 == +0, NaN
  * last; k > N pads with (-1, +inf).  Returns 0, or <0 on bad sizes / no memory. */

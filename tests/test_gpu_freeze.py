@@ -2,7 +2,8 @@
 (cm_freeze_stages, Sec. 3.2) on the GPU, through the C ABI.
 
 Per-stage costs: against the oracle's FP64 per-stage costs (bf16: on the
-bf16-rounded inputs).  A single stage lacks the averaging of the stage sum: a
+bf16-rounded inputs; FP8: the FP8 form's per-stage costs on the same codes,
+under each stage's share of the oracle's error bound).  A single stage lacks the averaging of the stage sum: a
 stage whose cost comes from one coefficient near cancellation (b_2 against
 W_2 h) carries that coefficient's relative error, so the per-stage bar is 10x
 the cost bar at the maximum (float32 1e-4, bf16 5e-3) while the median is
@@ -24,6 +25,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-4, "bf16": 5e-3}
 MEDIAN_TOL = {"fp32": 1e-6, "bf16": 2e-5}
+FP8_ACC_TOL = 2e-3  # as test_gpu_fp8.py: ACC_TOL
+FP8_TOL = 1e-5      # as test_gpu_fp8.py: FP8_TOL
 
 
 @pytest.fixture(scope="module")
@@ -48,17 +51,35 @@ def test_eval_stages_against_oracle(cm, oracle_mod, prec):
     rng = np.random.default_rng(41)
     qs = [draw_query(rng, S, N) for S, N in ((1, 5), (7, 33), (17, 100), (40, 70))]
     ws = gc.workspace_for(cm, qs)
-    batch, cost = cm.pack_queries(qs, prec, in_scale=16.0)
+    if prec == "fp8":  # both sides read the oracle's input codes
+        codes = [oracle_mod.fp8_codes(q.sched, 16.0) for q in qs]
+        batch, cost = gc.pack_fp8(cm, qs, codes)
+    else:
+        batch, cost = cm.pack_queries(qs, prec)
     stage = torch.full((sum(q.n_stages * q.n_cands for q in qs) + 8,), -7.0, device="cuda")
     cm.cm_eval_stages(m, prec, batch, ws, cost, stage)
     cost2 = torch.zeros_like(cost)
     cm.cm_eval_batch(m, prec, batch, ws, cost2)
     torch.cuda.synchronize()
     assert torch.equal(cost.view(torch.int32), cost2.view(torch.int32))
-    for q, d, sv in zip(qs, batch.queries, _stage_view(stage, batch)):
+    for j, (q, d, sv) in enumerate(zip(qs, batch.queries, _stage_view(stage, batch))):
         c = cost.cpu().numpy()[d[5]:d[5] + d[1]]
-        if prec == "fp8":  # no per-stage FP8 oracle: the stages must add up to the cost
-            assert np.allclose(sv.astype(np.float64).sum(0), c, rtol=1e-5)
+        assert np.allclose(sv.astype(np.float64).sum(0), c, rtol=1e-5)
+        if prec == "fp8":
+            # against the FP8 form's per-stage costs, under each stage's share
+            # of the oracle's bound (test_gpu_fp8.py: product sums off by
+            # ACC_TOL of their largest product, hoisted rows by 1e-5) plus
+            # FP8_TOL for the stage's float32 dot product; the typical stage
+            # takes no rounding flip and agrees to float32
+            _, _, ref_stage, sbound = oracle_mod.eval_query_fp8(
+                params, 16.0, 8.0, q.pipe, codes[j], q.terms, acc_tol=FP8_ACC_TOL,
+                stage_costs=True)
+            dev = np.abs(sv - ref_stage)
+            assert np.all(dev <= sbound + FP8_TOL * np.abs(ref_stage)), (q.n_stages, dev.max())
+            rel = np.where(ref_stage != 0, dev / np.where(ref_stage != 0, np.abs(ref_stage), 1.0),
+                           dev)
+            assert np.mean(rel <= FP8_TOL) >= 0.8 and np.median(rel) <= 2e-6, \
+                (q.n_stages, np.mean(rel <= FP8_TOL), np.median(rel))
             continue
         qq = gc.quantized(q) if prec == "bf16" else q
         ref, ref_stage = oracle_mod.eval_query(params, qq.pipe, qq.sched, qq.terms,

@@ -76,6 +76,12 @@ def test_fp8_form_hand_examples_exact(oracle_mod):
         for act_scale in (1.0, 4.0, 0.25):
             c = oracle_mod.eval_query_fp8(params, 1.0, act_scale, pipe, codes, terms)
             assert np.all(c == case["cost"]), (case["name"], act_scale, c)
+            # the per-stage costs (Sec. 5.2: the predictions that are summed)
+            c2, st = oracle_mod.eval_query_fp8(params, 1.0, act_scale, pipe, codes, terms,
+                                               stage_costs=True)
+            assert np.array_equal(c2, c)
+            want = np.repeat(np.array(case["stage_costs"])[:, None], st.shape[1], axis=1)
+            assert np.array_equal(st, want), (case["name"], act_scale, st)
 
 
 def test_fp8_form_quantizes_hidden_and_inputs(oracle_mod):
@@ -122,6 +128,15 @@ def test_fp8_form_invariants(oracle_mod):
     cp = np.random.default_rng(4).permutation(40)
     d = oracle_mod.eval_query_fp8(params, 4.0, 2.0, q.pipe, codes[:, cp], q.terms[:, cp])
     assert np.array_equal(d, a[cp])
+    # per-stage costs: non-negative, summed over stages they give the cost,
+    # and they follow a stage permutation exactly (a stage's cost depends on
+    # that stage's data only)
+    _, st = oracle_mod.eval_query_fp8(params, 4.0, 2.0, q.pipe, codes, q.terms, stage_costs=True)
+    assert np.all(st >= 0)
+    assert np.allclose(st.sum(axis=0), a, rtol=1e-12)
+    _, stp = oracle_mod.eval_query_fp8(params, 4.0, 2.0, q.pipe[perm], codes[perm], q.terms[perm],
+                                       stage_costs=True)
+    assert np.array_equal(stp, st[perm])
     assert np.all(a >= 0)
 
 
@@ -184,3 +199,13 @@ def test_fp8_error_bound(oracle_mod):
                                                       acc_tol=tau)
                     assert np.allclose(bd, flips + per_tau * tau, rtol=1e-9, atol=1e-12), \
                         (case["name"], b10, act_scale, tau, bd)
+                    # each stage's share: H1's stage as above; H2's second
+                    # stage 15 tau (3*1 + 6*2) plus 0.25 * |W_2[:, 0]| . (1, 2, 0)
+                    _, bd2, _, sb = oracle_mod.eval_query_fp8(
+                        params, 1.0, act_scale, pipe, codes, terms, acc_tol=tau, stage_costs=True)
+                    assert np.array_equal(bd2, bd)
+                    f1 = 252.5 if b10 else 0.0
+                    assert np.allclose(sb[0], f1 + 3630.0 * tau, rtol=1e-9, atol=1e-12)
+                    if case["name"] == "H2":
+                        assert np.allclose(sb[1], (0.25 if b10 else 0.0) + 15.0 * tau,
+                                           rtol=1e-9, atol=1e-12), (b10, tau, sb)

@@ -110,6 +110,11 @@ MUTANTS = [
     ("sample keeps the largest keys", "if (A->key != B->key) return A->key < B->key ? -1 : 1;",
      "if (A->key != B->key) return A->key > B->key ? -1 : 1;"),
     ("fp8 folded bias dropped", "u[s * H + h] = a + beta[h];", "u[s * H + h] = a + 0.0 * beta[h];"),
+    ("fp8 stage costs cumulative", "if (stage_cost_out != NULL) stage_cost_out[row] = v;",
+     "if (stage_cost_out != NULL) stage_cost_out[row] = stage_sum + v;"),
+    ("fp8 stage bound of the whole candidate",
+     "if (stage_bound_out != NULL) stage_bound_out[row] = sbound;",
+     "if (stage_bound_out != NULL) stage_bound_out[row] = bound + sbound;"),
 ]
 
 
