@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--latency-qps", type=float, default=2000.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-agreement", action="store_true",
+                    help="skip the served-beam agreement with the FP64 oracle")
+    ap.add_argument("--no-read-probe", action="store_true",
+                    help="skip the measured streaming-read roof")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
@@ -90,25 +94,64 @@ def traffic_record():
     return rec
 
 
+def draw_request(torch, S, N, seed, device):
+    """One request's float32 schedule features exp(N(4, 2^2)) and cost terms
+    exp(N(6, 1.5^2)), drawn on the GPU from their own seed, so that the
+    float32 originals of a bf16 request can be drawn again for the oracle."""
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    sched = torch.empty(S * N * 40, device=device).normal_(4.0, 2.0, generator=g).exp_()
+    terms = torch.empty(S * N * 8, device=device).normal_(6.0, 1.5, generator=g).exp_()
+    return sched, terms
+
+
 def session_inputs(torch, rng, n_sessions, per_session, device, seed):
     """Stage counts of the sessions and per-session request inputs drawn on
-    the GPU: (S, [(N, sched bf16, terms f32), ...]) per session."""
+    the GPU: (S, pipe, [(N, sched bf16, terms f32, seed), ...]) per session."""
     import numpy as np
     g = torch.Generator(device=device)
     g.manual_seed(seed)
     out = []
-    for _ in range(n_sessions):
+    for s in range(n_sessions):
         S = int(np.floor(np.exp(rng.uniform(np.log(3), np.log(121)))))
         reqs = []
-        for _ in range(per_session):
+        for j in range(per_session):
             N = int(rng.integers(16, 4097))
-            sched = torch.empty(S * N * 40, device=device).normal_(4.0, 2.0, generator=g)
-            sched = sched.exp_().to(torch.bfloat16)
-            terms = torch.empty(S * N * 8, device=device).normal_(6.0, 1.5, generator=g).exp_()
-            reqs.append((N, sched, terms))
+            rseed = seed * 100003 + s * 4099 + j
+            sched, terms = draw_request(torch, S, N, rseed, device)
+            reqs.append((N, sched.to(torch.bfloat16), terms, rseed))
+            del sched
         pipe = torch.poisson(torch.full((S * 56,), 3.0, device=device), generator=g)
         out.append((S, pipe.cpu().numpy().reshape(S, 56), reqs))
     return out
+
+
+def host_cpu():
+    """(threads this process may use, CPU model name) of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def probe_read_gbs(reps=10, gib=4):
+    """Median and best streaming-read GB/s of a plain read kernel of the
+    library's probe over `gib` GiB (far above the 256 MB last-level cache)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2012_07145_amd", "libcm_probe.so")
+    L = ctypes.CDLL(path)
+    L.cm_probe_read_gbs.argtypes = [ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    med, best = ctypes.c_double(), ctypes.c_double()
+    rc = L.cm_probe_read_gbs(gib << 30, reps, ctypes.byref(med), ctypes.byref(best))
+    if rc != 0:
+        raise RuntimeError(f"cm_probe_read_gbs failed ({rc})")
+    return med.value, best.value
 
 
 def main():
@@ -147,7 +190,7 @@ def main():
     log(f"generating inputs of {SESSIONS} sessions x {args.inputs_per_session} requests")
     sess_in = session_inputs(torch, rng, SESSIONS, args.inputs_per_session, dev, 5005)
     torch.cuda.synchronize()
-    in_bytes = sum(S * N * BYTES_PER_ROW_BF16 for S, _, reqs in sess_in for N, _, _ in reqs)
+    in_bytes = sum(S * N * BYTES_PER_ROW_BF16 for S, _, reqs in sess_in for N, *_ in reqs)
     log(f"{in_bytes / 1e9:.2f} GB of request inputs resident")
     srv = cm.cm_server_create(model, k=K, arena_bytes=16 << 30, max_slots=args.slots,
                               max_pending=8192, max_sessions=SESSIONS, max_stages=128,
@@ -221,6 +264,11 @@ def main():
     bytes_per_launch = st["kernel_bytes"] / launches
     achieved = st["kernel_bytes"] / (st["kernel_us"] * 1e-6) / 1e9 if st["kernel_us"] else 0.0
     tr = traffic_record()
+    read_roof = None
+    if not args.no_read_probe:
+        read_roof = probe_read_gbs()
+        log(f"streaming-read probe: {read_roof[0]:.0f} GB/s median, {read_roof[1]:.0f} best; "
+            f"k_step_bf16 {achieved:.0f} GB/s = {achieved / read_roof[0]:.3f} of it")
 
     # ------------------------------------------------------------ latency
     latency = None
@@ -243,7 +291,7 @@ def main():
                 tickets = []
                 srv.reset_stats()
             s = int(who[i])
-            N, sched, terms = sess_in[s][2][int(pick[i])]
+            N, sched, terms, _ = sess_in[s][2][int(pick[i])]
             tickets.append(srv.submit(sids[s], N, sched, terms, K))
         srv.wait_all(np.array(tickets, np.uint64), 120000)
         ls = srv.stats()
@@ -253,22 +301,62 @@ def main():
                    "micro_batches": ls["micro_batches"]}
         log(f"latency at {args.latency_qps:.0f} q/s: p50 {ls['p50_us']:.0f} us, "
             f"p99 {ls['p99_us']:.0f} us over {ls['completed']} queries")
-    # served beams of a sample of requests against the FP64 oracle on the same
-    # inputs (drawn as bf16, so these are the original values)
+    # served beams of every request of every input set against the FP64
+    # oracle, on two readings: the float32 originals the bf16 features were
+    # rounded from (the headline reading) and the bf16-rounded features the
+    # server reads (its arithmetic alone).  The server's beams do not depend on
+    # batching, so these are the beams of the timed steps.
     import oracle
-    s_hit = s_tot = 0
+    agree = None
+    if not args.no_agreement:
+        t_ag = time.perf_counter()
+        hits = {"f32": 0, "bf16": 0}
+        tot = 0
+        worst_bf16 = worst_f32 = 0.0
+        n_req = 0
+        for j in range(args.inputs_per_session):
+            ns, sp, tp, _, _ = steps_pre[j]
+            tickets = srv.submit_batch(sids, ns, sp, tp, K)
+            beams = srv.wait_all_results(tickets, 120000)
+            for s_, (idx, val) in enumerate(beams):
+                S, pipe, reqs = sess_in[s_]
+                N, sched16, terms, rseed = reqs[j]
+                x32, _ = draw_request(torch, S, N, rseed, dev)
+                x32 = x32.cpu().numpy().reshape(S, N, 40)
+                t_h = terms.cpu().numpy().reshape(S, N, 8)
+                x16 = sched16.float().cpu().numpy().reshape(S, N, 40)
+                kk = min(K, N)
+                sel = idx[:kk].tolist()
+                for name, x in (("f32", x32), ("bf16", x16)):
+                    ref = oracle.eval_query(params, pipe, x, t_h)
+                    top = np.lexsort((np.arange(N), ref))[:kk]
+                    hits[name] += len(set(sel) & set(top.tolist()))
+                    rel = float(np.max(np.abs(val[:kk].astype(np.float64) - ref[idx[:kk]]) /
+                                       np.abs(ref[idx[:kk]])))
+                    if name == "f32":
+                        worst_f32 = max(worst_f32, rel)
+                    else:
+                        worst_bf16 = max(worst_bf16, rel)
+                tot += kk
+                n_req += 1
+        agree = {"requests": n_req, "selections": tot,
+                 "vs_fp64_f32_inputs": hits["f32"] / tot, "hits_f32_inputs": [hits["f32"], tot],
+                 "vs_fp64_bf16_inputs": hits["bf16"] / tot, "hits_bf16_inputs": [hits["bf16"], tot],
+                 "max_rel_err_beam_vs_fp64_f32_inputs": worst_f32,
+                 "max_rel_err_beam_vs_fp64_bf16_inputs": worst_bf16,
+                 "meets_999": hits["f32"] / tot >= 0.999,
+                 "seconds": time.perf_counter() - t_ag}
+        log(f"served beams ({n_req} requests, {tot} selections) vs FP64: top-32 agreement "
+            f"{hits['f32']}/{tot} = {hits['f32'] / tot:.5f} on the float32 originals, "
+            f"{hits['bf16']}/{tot} = {hits['bf16'] / tot:.5f} on the bf16 inputs "
+            f"({agree['seconds']:.0f} s)")
+    # a bounded sample for the CPU baseline: the first request of 8 sessions
     sample = []
-    for s in range(8):
-        S, pipe, reqs = sess_in[s]
-        N, sched, terms = reqs[0]
-        idx, _, _ = srv.wait(srv.submit(sids[s], N, sched, terms, K), 120000)
-        x = (pipe, sched.float().cpu().numpy().reshape(S, N, 40), terms.cpu().numpy().reshape(S, N, 8))
-        sample.append(x)
-        oi, _ = oracle.select(oracle.eval_query(params, *x), K)
-        kk = min(K, N)
-        s_hit += len(set(idx[:kk].tolist()) & set(oi[:kk].tolist()))
-        s_tot += kk
-    log(f"served beams vs FP64 on the same inputs: top-32 agreement {s_hit}/{s_tot}")
+    for s_ in range(8):
+        S, pipe, reqs = sess_in[s_]
+        N, sched, terms, _ = reqs[0]
+        sample.append((pipe, sched.float().cpu().numpy().reshape(S, N, 40),
+                       terms.cpu().numpy().reshape(S, N, 8)))
     srv.close()
 
     # ------------------------------------------------------------ ragged step
@@ -327,21 +415,36 @@ def main():
     # ------------------------------------------------------------ cpu baseline
     cpu = None
     if not args.no_cpu_baseline:
-        # a bounded sample of the serving workload: the 8 requests above
-        # (features read back, bf16 widened to float32)
+        # a bounded sample of the serving workload: the first request of 8
+        # sessions (bf16 features widened to float32), FP64 evaluation +
+        # stable selection, on every thread of this process and on one
+        import oracle
         n_s = sum(x[1].shape[1] for x in sample)
         rows_s = sum(x[1].shape[0] * x[1].shape[1] for x in sample)
-        reps, t_start = 0, time.perf_counter()
-        while reps == 0 or time.perf_counter() - t_start < args.cpu_seconds:
-            for pipe, sched, terms in sample:
-                oracle.select(oracle.eval_query(params, pipe, sched, terms), K)
-            reps += 1
-        dt = time.perf_counter() - t_start
-        cpu = {"value": reps * n_s / dt, "unit": "candidates/s",
-               "cores": oracle.lib().max_threads(), "kind": "oracle",
+        nproc, cpu_model = host_cpu()
+
+        def timed_oracle(nthreads, seconds):
+            reps, t_start = 0, time.perf_counter()
+            while reps == 0 or time.perf_counter() - t_start < seconds:
+                for pipe, sched, terms in sample:
+                    oracle.select(oracle.eval_query(params, pipe, sched, terms, nthreads=nthreads), K)
+                reps += 1
+            return reps, time.perf_counter() - t_start
+
+        threads = oracle.lib().max_threads()
+        reps_all, dt_all = timed_oracle(0, args.cpu_seconds)
+        reps_one, dt_one = timed_oracle(1, args.cpu_seconds)
+        cpu = {"value": reps_all * n_s / dt_all, "unit": "candidates/s",
+               "cores": threads, "kind": "oracle",
                "sample": f"8 serving requests ({n_s} candidates, {rows_s} rows), FP64 "
-                         f"evaluation + stable selection, {reps} passes in {dt:.1f} s"}
-        log(f"cpu oracle: {cpu['value']:.0f} candidates/s on {cpu['cores']} threads")
+                         f"evaluation + stable selection, {reps_all} passes in {dt_all:.1f} s "
+                         f"on {threads} threads",
+               "single_thread": {"value": reps_one * n_s / dt_one, "unit": "candidates/s",
+                                 "cores": 1, "passes": reps_one, "seconds": dt_one},
+               "rows_per_s": reps_all * rows_s / dt_all,
+               "host": {"nproc": nproc, "cpu_model": cpu_model}}
+        log(f"cpu oracle: {cpu['value']:.0f} candidates/s on {threads} threads, "
+            f"{cpu['single_thread']['value']:.0f} on 1 ({cpu_model}, nproc {nproc})")
 
     # ------------------------------------------------------------ bf16 vs fp8
     precision = None
@@ -455,16 +558,17 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],
                      "kernel": "k_step_bf16", "avg_launch_us": avg_us,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "launches": launches},
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "launches": launches,
+                     "measured_read_gbs": None if read_roof is None else read_roof[0],
+                     "frac_of_measured_read": None if read_roof is None else achieved / read_roof[0]},
         "cpu_baseline": cpu,
         "fp32_plain": fp32,
         "bf16_over_fp32_plain": None if fp32 is None else value / fp32["candidates_per_s"],
         "serving_step_tuning": tune,
         "ragged_step": ragged,
         "precision": precision,
-        "serving_top32_agreement_vs_fp64": s_hit / s_tot,
-        "serving_top32_hits": [s_hit, s_tot],
-        "top32_agreement_vs_fp64": None if ragged is None else ragged["top32_agreement_vs_fp64"],
+        "serving_agreement": agree,
+        "top32_agreement_vs_fp64": None if agree is None else agree["vs_fp64_f32_inputs"],
         "selection_bit_exact": None if ragged is None else ragged["selection_bit_exact"],
     }
     print(json.dumps(out), flush=True)

@@ -595,6 +595,13 @@ cm_status cm_serve_wait_all(cm_server *server, int32_t n, const uint64_t *ticket
 cm_status cm_server_get_stats(cm_server *server, cm_server_stats *out);
 /* Clears the counters and latencies (not the queue or arena state). */
 cm_status cm_server_reset_stats(cm_server *server);
+/* Failure handling, forced from the host: the server's next micro-batch
+ * launch fails as if the device had refused it (nothing is launched).  The
+ * server then enters its failed state: every queued and admitted request
+ * returns CM_EDEVICE from poll and wait, and later submissions and session
+ * openings return CM_EDEVICE.  For tests of callers' error paths; a failed
+ * server can only be destroyed.  Errors: CM_EINVAL. */
+cm_status cm_server_fail_next_launch(cm_server *server);
 
 /* Launch configuration of the server's steps (every slot; see
  * cm_step_config), for example the one cm_step_autotune or a short trial

@@ -435,6 +435,21 @@ class Server:
         check(lib().cm_serve_wait_all(self.handle, len(t), t.ctypes.data_as(ctypes.c_void_p),
                                       int(timeout_ms), None))
 
+    def wait_all_results(self, tickets, timeout_ms: int = 60000):
+        """Wait for every ticket and release them; returns [(idx, val), ...]
+        in ticket order (each the request's beam)."""
+        t = np.ascontiguousarray(tickets, dtype=np.uint64)
+        n = len(t)
+        outs = (_lib.cm_result * max(n, 1))()
+        bufs = []
+        for j in range(n):
+            res, idx, val = self._result(self.k)
+            outs[j] = res
+            bufs.append((idx, val))
+        check(lib().cm_serve_wait_all(self.handle, n, t.ctypes.data_as(ctypes.c_void_p),
+                                      int(timeout_ms), outs))
+        return [(idx[:outs[j].n], val[:outs[j].n]) for j, (idx, val) in enumerate(bufs)]
+
     def stats(self) -> dict:
         s = _lib.cm_server_stats()
         check(lib().cm_server_get_stats(self.handle, ctypes.byref(s)))
@@ -442,6 +457,10 @@ class Server:
 
     def reset_stats(self):
         check(lib().cm_server_reset_stats(self.handle))
+
+    def fail_next_launch(self):
+        """The next micro-batch launch fails (forced from the host)."""
+        check(lib().cm_server_fail_next_launch(self.handle))
 
     def set_step_config(self, grid=0, group_tiles=1, use_graph=1):
         c = _lib.cm_step_config(int(grid), int(group_tiles), int(use_graph))

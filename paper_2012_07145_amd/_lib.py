@@ -31,7 +31,7 @@ EXPORTS = (
     "cm_server_create", "cm_server_destroy", "cm_session_open", "cm_session_close",
     "cm_session_beam", "cm_serve_submit", "cm_serve_poll", "cm_serve_wait",
     "cm_serve_submit_batch", "cm_serve_wait_all",
-    "cm_server_get_stats", "cm_server_reset_stats",
+    "cm_server_get_stats", "cm_server_reset_stats", "cm_server_fail_next_launch",
     "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
     "cm_sampler_create", "cm_sampler_destroy", "cm_sample_buckets",
@@ -154,6 +154,7 @@ def lib():
         L.cm_serve_wait_all.argtypes = [vp, i32, vp, i32, ctypes.POINTER(cm_result)]
         L.cm_server_get_stats.argtypes = [vp, ctypes.POINTER(cm_server_stats)]
         L.cm_server_reset_stats.argtypes = [vp]
+        L.cm_server_fail_next_launch.argtypes = [vp]
         fl = ctypes.c_float
         L.cm_model_prepare_fp8.argtypes = [vp, fl, fl]
         L.cm_fp8_calibrate.argtypes = [vp, i64, vp, vp, ctypes.POINTER(fl), ctypes.POINTER(fl)]

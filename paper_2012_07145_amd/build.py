@@ -16,9 +16,12 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcm.so")
+# the benchmark's streaming-read probe (not part of the cost-model path)
+PROBE_LIB = os.path.join(PKG, "libcm_probe.so")
+PROBE_SOURCES = ["probe_read.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cm_api.hip", "cm_step.hip", "cm_serve.hip", "k_plain.hip", "k_bf16.hip", "k_topk.hip", "k_step.hip", "k_fp8.hip", "k_freeze.hip", "k_penalty.hip", "cm_sample.hip"]
+SOURCES = ["cm_api.hip", "cm_step.hip", "cm_serve.hip", "serve_core.cpp", "k_plain.hip", "k_bf16.hip", "k_topk.hip", "k_step.hip", "k_fp8.hip", "k_freeze.hip", "k_penalty.hip", "cm_sample.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -50,11 +53,17 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmds.append([HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    pobjs = []
+    for src in PROBE_SOURCES:
+        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        pobjs.append(obj)
+        cmds.append([HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
-    tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
-    os.replace(tmp, LIB)
+    for lib, o in ((LIB, objs), (PROBE_LIB, pobjs)):
+        tmp = lib + ".tmp"
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *o, "-o", tmp], verbose)
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -250,3 +250,81 @@ def test_serve_submit_batch_and_wait_all(cm, model):
         ri, rv = _alone(cm, model, q, k)
         assert np.array_equal(bi, ri) and _same(bv, rv), sid
     srv.close()
+
+
+def test_served_beams_against_oracle(cm, model, oracle_mod):
+    """Served beams against the FP64 oracle (Sec. 4: the search keeps the k
+    best states; Sec. 4.4: evaluated candidates are added to the beam), on
+    the bf16-rounded inputs the server reads: 96 requests from 24 sessions
+    through continuous batching.  Every served value is within the bf16 bar
+    (5e-4 relative, as the per-call parity tests) of the oracle's cost of that
+    candidate, each beam is sorted by (cost, index) and padded with (-1, +inf)
+    below k, and the served beams agree with the oracle's own top-k on at
+    least 99.9% of the pooled selections."""
+    from tests import gpucase as gc
+    rng = np.random.default_rng(62)
+    k = 32
+    params = model_params(bias=True)
+    srv = cm.cm_server_create(model, k=k, max_slots=3, max_sessions=24, max_batch_queries=16,
+                              max_batch_cands=1 << 16)
+    sess = _sessions(cm, srv, rng, 24)
+    reqs = []
+    for r in range(96):
+        sid, pipe = sess[r % len(sess)]
+        base = draw_query(rng, pipe.shape[0], int(rng.integers(16, 3000)))
+        q = Query(pipe, base.sched, base.terms)
+        reqs.append((sid, q) + _device_inputs(q))
+    tickets = srv.submit_batch([r[0] for r in reqs], [r[1].n_cands for r in reqs],
+                               [r[2].data_ptr() for r in reqs], [r[3].data_ptr() for r in reqs], k)
+    hit = tot = 0
+    worst = 0.0
+    for t, (sid, q, _, _) in zip(tickets, reqs):
+        idx, val, _ = srv.wait(int(t), 60000)
+        qq = gc.quantized(q)
+        ref = oracle_mod.eval_query(params, qq.pipe, qq.sched, qq.terms)
+        kk = min(k, q.n_cands)
+        assert np.all(idx[kk:] == -1) and np.all(np.isinf(val[kk:])), sid
+        got = val[:kk].astype(np.float64)
+        err = np.abs(got - ref[idx[:kk]]) / np.abs(ref[idx[:kk]])
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 5e-4, (sid, q.n_stages, q.n_cands, err.max())
+        order = np.lexsort((idx[:kk], got))
+        assert np.array_equal(order, np.arange(kk)), sid  # ascending (cost, index)
+        top = np.lexsort((np.arange(q.n_cands), ref))[:kk]
+        hit += len(set(idx[:kk].tolist()) & set(top.tolist()))
+        tot += kk
+    print(f"\nserved beams vs FP64 on bf16 inputs: {hit}/{tot} = {hit / tot:.5f}, "
+          f"max rel err {worst:.2e}")
+    assert hit / tot >= 0.999, (hit, tot)
+    srv.close()
+
+
+def test_serve_forced_launch_failure(cm, model):
+    """Failure handling forced from the host (no device fault): after
+    cm_server_fail_next_launch, the next micro-batch is not launched, every
+    queued and admitted request returns CM_EDEVICE, and so do later
+    submissions; the failed server is destroyed cleanly."""
+    rng = np.random.default_rng(63)
+    srv = cm.cm_server_create(model, k=8, max_slots=2, max_sessions=8, max_batch_queries=4,
+                              max_batch_cands=1 << 14)
+    sess = _sessions(cm, srv, rng, 6)
+    reqs = []
+    for sid, pipe in sess:
+        base = draw_query(rng, pipe.shape[0], 200)
+        q = Query(pipe, base.sched, base.terms)
+        reqs.append((sid, q) + _device_inputs(q))
+    # one request that completes normally first
+    idx, val, _ = srv.wait(srv.submit(reqs[0][0], 200, reqs[0][2], reqs[0][3], 8), 20000)
+    ri, rv = _alone(cm, model, reqs[0][1], 8)
+    assert np.array_equal(idx, ri) and _same(val, rv)
+    srv.fail_next_launch()
+    tickets = srv.submit_batch([r[0] for r in reqs], [200] * len(reqs),
+                               [r[2].data_ptr() for r in reqs], [r[3].data_ptr() for r in reqs], 8)
+    for t in tickets:
+        with pytest.raises(cm.CmError, match="CM_EDEVICE"):
+            srv.wait(int(t), 20000)
+    with pytest.raises(cm.CmError, match="CM_EDEVICE"):
+        srv.submit(reqs[1][0], 200, reqs[1][2], reqs[1][3], 8)
+    st = srv.stats()
+    assert st["completed"] == 1
+    srv.close()
