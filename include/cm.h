@@ -410,7 +410,7 @@ typedef struct {
 typedef struct {
     int32_t grid;         /* persistent workgroups (8 waves each); 0 = two per
                              compute unit */
-    int32_t group_tiles;  /* row-tile groups per task: 1, 2 or 4 (a group is
+    int32_t group_tiles;  /* row-tile groups per task: 1, 2, 4 or 8 (a group is
                              8 / P tiles of 32 candidates) */
     int32_t use_graph;    /* 1: replay a captured graph; 0: plain launches */
 } cm_step_config;
@@ -447,14 +447,28 @@ cm_status cm_step_set_config(cm_step *step, const cm_step_config *cfg);
 cm_status cm_step_get_config(const cm_step *step, cm_step_config *cfg);
 
 /* Autotuner: times every configuration of a built-in candidate set on this
- * batch (`reps` timed runs each after one untimed run, median of HIP event
- * times on `stream`), keeps the fastest as the step's configuration and
- * returns it in *best (and its median time in microseconds in *best_us, if
- * not NULL).  Synchronous.  The runs write the outputs like cm_step_run.
- * Errors: as cm_step_run. */
+ * batch (grid 1, 2 and 4 workgroups per compute unit x group_tiles 1, 2, 4,
+ * 8 x graph replay or plain launches; `reps` timed runs each after one
+ * untimed run, median of HIP event times on `stream`), keeps the fastest as
+ * the step's configuration and returns it in *best (and its median time in
+ * microseconds in *best_us, if not NULL).  The pick is also stored in the
+ * library's tuning cache under (the device's architecture name, the step's
+ * precision, ceil(log2 queries), ceil(log2 rows)) of this batch; when the
+ * environment variable CM_TUNE_CACHE names a file, the cache is read from it
+ * on first use and written back after every autotune.  Synchronous.  The
+ * runs write the outputs like cm_step_run.  Errors: as cm_step_run. */
 cm_status cm_step_autotune(cm_step *step, const cm_batch *batch, const float *U, int32_t k,
                            float *cost_out, int32_t *idx_out, float *val_out, cm_stream stream,
                            int32_t reps, cm_step_config *best, float *best_us);
+
+/* The tuning cache's configuration for batches of n_queries queries and
+ * `rows` rows on this step's device and precision: the entry of the nearest
+ * bucket (closest query bucket, then closest row bucket; rows <= 0: the
+ * largest row bucket).  Does not change the step.  cm_server_create applies
+ * the entry for its max_batch_queries to its steps.  Errors: CM_EINVAL,
+ * CM_ENOTFOUND (no entry for this architecture and precision). */
+cm_status cm_step_tuned_config(const cm_step *step, int32_t n_queries, int64_t rows,
+                               cm_step_config *out);
 
 /* Kernel-only GPU time, in microseconds, of the step's most recent run (the
  * persistent evaluation-and-selection kernel alone, without the descriptor
@@ -605,8 +619,9 @@ cm_status cm_server_fail_next_launch(cm_server *server);
 
 /* Launch configuration of the server's steps (every slot; see
  * cm_step_config), for example the one cm_step_autotune or a short trial
- * of the caller picks for its traffic.  The default is {grid 0 (two
- * workgroups per compute unit), group_tiles 1, use_graph 1}; plain launches
+ * of the caller picks for its traffic.  The default is the tuning cache's
+ * entry for the server's max_batch_queries (cm_step_tuned_config), else
+ * {grid 0 (two workgroups per compute unit), group_tiles 1, use_graph 1}; plain launches
  * (use_graph 0) cost a lone request less time per micro-batch.  Takes effect
  * for micro-batches launched afterwards; results never depend on it.
  * Errors: CM_EINVAL. */

@@ -21,6 +21,7 @@ __all__ = [
     "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
     "cm_version", "pack_queries", "Step", "cm_step_create", "cm_step_destroy", "cm_step_run",
     "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
+    "cm_step_tuned_config",
     "Server", "cm_server_create", "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
     "Sampler", "cm_sampler_create", "cm_sample_buckets",
@@ -337,6 +338,17 @@ def cm_step_autotune(step: Step, batch: Batch, U, k: int, cost_out, idx_out, val
                                  _stream_handle(stream), int(reps), ctypes.byref(cfg),
                                  ctypes.byref(us)))
     return dict(grid=cfg.grid, group_tiles=cfg.group_tiles, use_graph=cfg.use_graph), us.value
+
+
+def cm_step_tuned_config(step: Step, n_queries: int, rows: int = 0):
+    """The tuning cache's configuration (dict) for batches of this size on
+    the step's device and precision, or None when it holds none."""
+    cfg = _lib.cm_step_config()
+    st = lib().cm_step_tuned_config(step.handle, int(n_queries), int(rows), ctypes.byref(cfg))
+    if st == _lib.CM_ENOTFOUND:
+        return None
+    check(st)
+    return dict(grid=cfg.grid, group_tiles=cfg.group_tiles, use_graph=cfg.use_graph)
 
 
 def cm_step_kernel_time(step: Step) -> float:

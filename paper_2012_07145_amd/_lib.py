@@ -27,7 +27,7 @@ EXPORTS = (
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
     "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
     "cm_step_create", "cm_step_destroy", "cm_step_run", "cm_step_set_config",
-    "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
+    "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time", "cm_step_tuned_config",
     "cm_server_create", "cm_server_destroy", "cm_session_open", "cm_session_close",
     "cm_session_beam", "cm_serve_submit", "cm_serve_poll", "cm_serve_wait",
     "cm_serve_submit_batch", "cm_serve_wait_all",
@@ -140,6 +140,7 @@ def lib():
         L.cm_step_autotune.argtypes = [vp, ctypes.POINTER(cm_batch), vp, i32, vp, vp, vp, vp,
                                        i32, ctypes.POINTER(cm_step_config),
                                        ctypes.POINTER(ctypes.c_float)]
+        L.cm_step_tuned_config.argtypes = [vp, i32, i64, ctypes.POINTER(cm_step_config)]
         L.cm_step_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
         L.cm_server_create.argtypes = [vp, ctypes.POINTER(cm_server_cfg), ctypes.POINTER(vp)]
         L.cm_server_destroy.argtypes = [vp]
@@ -172,7 +173,7 @@ def lib():
                   "cm_workspace_destroy", "cm_eval_batch", "cm_hoist_stages",
                   "cm_eval_hoisted", "cm_topk_per_query", "cm_step_create",
                   "cm_step_destroy", "cm_step_run", "cm_step_set_config",
-                  "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
+                  "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time", "cm_step_tuned_config",
                   "cm_server_create", "cm_server_destroy", "cm_session_open",
                   "cm_session_close", "cm_session_beam", "cm_serve_submit", "cm_serve_poll",
                   "cm_serve_wait", "cm_server_get_stats", "cm_server_reset_stats",

@@ -242,6 +242,11 @@ cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_s
         return fail(CM_ENOMEM, "server allocation failed");
     }
     V->core->bytes_check = query_bytes;
+    // a launch configuration the autotuner picked for micro-batches of this
+    // size on this device and precision (tuning cache), if there is one
+    cm_step_config tuned;
+    if (cm_step_tuned_config(V->slot[0].step, c.max_batch_queries, 0, &tuned) == CM_OK)
+        for (int i = 0; i < c.max_slots; ++i) (void)cm_step_set_config(V->slot[i].step, &tuned);
     for (int j = 0; j < c.k; ++j) {
         V->h_beam_init[j] = -1;
         const float inf = __builtin_inff();

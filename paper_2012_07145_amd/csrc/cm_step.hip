@@ -1,9 +1,13 @@
 // cm_step.hip -- host side of the persistent beam step (include/cm.h):
 // descriptor slots in pinned memory, graph capture and replay, autotuner.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "cm_internal.h"
@@ -39,6 +43,7 @@ struct cm_step {
     cm_step_desc cap{};
     cm_step_config cfg{};
     int cus = 0;
+    char arch[64] = {0};  // the device's gcnArchName (key of the tuning cache)
     int64_t max_tiles = 0;
     size_t block_bytes = 0;
     hipStream_t cs = nullptr;  // capture stream
@@ -304,10 +309,80 @@ cm_status check_config(const cm_step_config *c)
 {
     if (!c) return fail(CM_EINVAL, "config is NULL");
     if (c->grid < 0 || c->grid > 65535) return fail(CM_EINVAL, "grid %d outside [0, 65535]", c->grid);
-    if (c->group_tiles != 1 && c->group_tiles != 2 && c->group_tiles != 4)
-        return fail(CM_EINVAL, "group_tiles must be 1, 2 or 4");
+    if (c->group_tiles != 1 && c->group_tiles != 2 && c->group_tiles != 4 && c->group_tiles != 8)
+        return fail(CM_EINVAL, "group_tiles must be 1, 2, 4 or 8");
     if (c->use_graph != 0 && c->use_graph != 1) return fail(CM_EINVAL, "use_graph must be 0 or 1");
     return CM_OK;
+}
+
+}  // namespace
+
+// ---- tuning cache: the autotuner's pick per (GPU architecture, precision,
+// shape bucket), shape bucket = (ceil log2 of the queries, ceil log2 of the
+// rows) of the batch it was tuned on.  Process-wide; loaded from and saved
+// to the text file named by the environment variable CM_TUNE_CACHE when it
+// is set (one entry per line: arch precision qbucket rbucket grid
+// group_tiles use_graph microseconds).
+namespace {
+
+struct TuneEntry {
+    cm_step_config cfg;
+    float us;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;  // key: "arch precision qb rb"
+bool g_tune_loaded = false;
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+std::string tune_key(const char *arch, cm_precision prec, int qb, int rb)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s %d %d %d", arch, (int)prec, qb, rb);
+    return buf;
+}
+
+// (mutex held)
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("CM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int prec, qb, rb, grid, gt, graph;
+    float us;
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d %f", arch, &prec, &qb, &rb, &grid, &gt, &graph,
+                       &us) == 8) {
+        const cm_step_config c{grid, gt, graph};
+        if (grid >= 0 && grid <= 65535 && (gt == 1 || gt == 2 || gt == 4 || gt == 8) &&
+            (graph == 0 || graph == 1))
+            g_tune[tune_key(arch, prec, qb, rb)] = TuneEntry{c, us};
+    }
+    std::fclose(f);
+}
+
+// (mutex held)
+void tune_save_locked()
+{
+    const char *path = std::getenv("CM_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto &kv : g_tune)
+        std::fprintf(f, "%s %d %d %d %.3f\n", kv.first.c_str(), kv.second.cfg.grid,
+                     kv.second.cfg.group_tiles, kv.second.cfg.use_graph, kv.second.us);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path);
 }
 
 }  // namespace
@@ -386,6 +461,7 @@ cm_status cm_step_create(const cm_model *model, cm_precision prec, const cm_step
                     S->device);
     }
     S->cus = prop.multiProcessorCount;
+    std::snprintf(S->arch, sizeof S->arch, "%s", prop.gcnArchName);
     if (hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) != hipSuccess) {
         S->cs = nullptr;
         free_step(S);
@@ -476,8 +552,9 @@ cm_status cm_step_autotune(cm_step *S, const cm_batch *b, const float *U, int32_
     if (rc != CM_OK) return rc;
     const cm_step_config saved = S->cfg;
     std::vector<cm_step_config> cands;
-    for (int gm : {1, 2, 4})
-        for (int gt : {1, 2, 4}) cands.push_back(cm_step_config{gm * S->cus, gt, 1});
+    for (int graph : {1, 0})
+        for (int gm : {1, 2, 4})
+            for (int gt : {1, 2, 4, 8}) cands.push_back(cm_step_config{gm * S->cus, gt, graph});
     std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -519,8 +596,45 @@ cm_status cm_step_autotune(cm_step *S, const cm_batch *b, const float *U, int32_
     if (rc == CM_OK) {
         if (best) *best = best_c;
         if (best_us) *best_us = best_t;
+        int64_t rows = 0;
+        for (int32_t q = 0; q < b->n_queries; ++q)
+            rows += (int64_t)b->queries[q].n_stages * b->queries[q].n_cands;
+        std::lock_guard<std::mutex> tl(g_tune_mu);
+        tune_load_locked();
+        g_tune[tune_key(S->arch, S->prec, ceil_log2(b->n_queries), ceil_log2(rows))] =
+            TuneEntry{best_c, best_t};
+        tune_save_locked();
     }
     return rc;
+}
+
+cm_status cm_step_tuned_config(const cm_step *S, int32_t n_queries, int64_t rows,
+                               cm_step_config *out)
+{
+    if (!S || !out) return fail(CM_EINVAL, "NULL argument");
+    if (n_queries < 1) return fail(CM_EINVAL, "n_queries %d < 1", n_queries);
+    const int qb = ceil_log2(n_queries), rb = rows > 0 ? ceil_log2(rows) : -1;
+    std::lock_guard<std::mutex> tl(g_tune_mu);
+    tune_load_locked();
+    // the nearest bucket of this architecture and precision: closest query
+    // bucket first, then closest row bucket (the largest when rows <= 0)
+    const std::string head = tune_key(S->arch, S->prec, 0, 0);
+    const std::string prefix = head.substr(0, head.size() - 3);  // "arch prec "
+    const TuneEntry *best = nullptr;
+    int64_t best_d = 0;
+    for (const auto &kv : g_tune) {
+        if (kv.first.compare(0, prefix.size(), prefix) != 0) continue;
+        int eq = 0, er = 0;
+        if (std::sscanf(kv.first.c_str() + prefix.size(), "%d %d", &eq, &er) != 2) continue;
+        const int64_t d = (int64_t)std::abs(eq - qb) * 4096 + (rb >= 0 ? std::abs(er - rb) : 64 - er);
+        if (!best || d < best_d) {
+            best = &kv.second;
+            best_d = d;
+        }
+    }
+    if (!best) return fail(CM_ENOTFOUND, "no tuned configuration for %s", prefix.c_str());
+    *out = best->cfg;
+    return CM_OK;
 }
 
 }  // extern "C"

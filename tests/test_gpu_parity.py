@@ -153,6 +153,12 @@ def test_ragged_batch_alone_equals_in_mix(cm, oracle_mod):
     print(f"\nragged_17q bf16 top-32 agreement: {a_q:.4f} vs FP64 on bf16 inputs, "
           f"{a:.4f} ({hit}/{tot}) vs FP64 on float32 inputs")
     assert a_q >= 0.999
+    # Against FP64 on the float32 originals the agreement is set by the bf16
+    # rounding of the inputs (the precision form's own quantization), not by
+    # the arithmetic (a_q above).  This batch has 544 selections, where one
+    # miss is 0.18%, so it cannot resolve the metric's 0.1%; the benchmark
+    # measures this reading on every served request (about 32,000
+    # selections) and reports it.  Here it is a regression guard only.
     assert a >= 0.995
     ws.close()
     m.close()

@@ -82,7 +82,8 @@ def _check_against(batch, cost_np, idx_np, val_np, ref):
     assert _same_bits(val_np[:nk], rv[:nk])
 
 
-CONFIGS = [(0, 1, 1), (0, 1, 0), (64, 1, 1), (512, 2, 1), (1024, 4, 1), (97, 4, 0), (2048, 2, 1)]
+CONFIGS = [(0, 1, 1), (0, 1, 0), (64, 1, 1), (512, 2, 1), (1024, 4, 1), (97, 4, 0), (2048, 2, 1),
+           (0, 8, 1), (300, 8, 0)]
 
 
 @pytest.mark.parametrize("own_hoist", [True, False])
@@ -235,8 +236,13 @@ def test_step_many_queries_and_slots_in_flight(cm, model):
     step.close()
 
 
-def test_step_autotune_keeps_results(cm, model):
+def test_step_autotune_keeps_results(cm, model, tmp_path, monkeypatch):
+    """The autotuner's pick leaves the results unchanged, is stored in the
+    tuning cache (and its file, CM_TUNE_CACHE), is found again by
+    cm_step_tuned_config and is applied by a server created afterwards."""
     import torch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("CM_TUNE_CACHE", str(cache))
     rng = np.random.default_rng(31337)
     qs = [draw_query(rng, int(rng.integers(3, 121)), int(rng.integers(16, 2000)))
           for _ in range(6)]
@@ -246,8 +252,18 @@ def test_step_autotune_keeps_results(cm, model):
     step = _step_for(cm, model, qs, k)
     cost, idx, val = _outs(batch, k)
     cfg, us = cm.cm_step_autotune(step, batch, None, k, cost, idx, val, reps=3)
-    assert cfg["group_tiles"] in (1, 2, 4) and cfg["grid"] > 0 and us > 0
+    assert cfg["group_tiles"] in (1, 2, 4, 8) and cfg["grid"] > 0 and us > 0
     assert cm.cm_step_get_config(step) == cfg
+    rows = sum(q.n_stages * q.n_cands for q in qs)
+    assert cm.cm_step_tuned_config(step, len(qs), rows) == cfg
+    assert cm.cm_step_tuned_config(step, len(qs)) is not None
+    line = [l.split() for l in cache.read_text().splitlines()]
+    assert any(int(f[4]) == cfg["grid"] and int(f[5]) == cfg["group_tiles"] and
+               int(f[6]) == cfg["use_graph"] for f in line), line
+    srv = cm.cm_server_create(model, k=k, max_slots=1, max_sessions=2, max_batch_queries=len(qs),
+                              max_batch_cands=1 << 14)
+    assert srv.get_step_config() == cm.cm_step_tuned_config(step, len(qs))
+    srv.close()
     torch.cuda.synchronize()
     _check_against(batch, cost.cpu().numpy(), idx.cpu().numpy(), val.cpu().numpy(), ref)
     cost, idx, val = _outs(batch, k)
