@@ -340,14 +340,12 @@ void test_failed_micro_batch()
     s.ex.fail_poll_at = 1;  // the second micro-batch fails on the device
     std::vector<int32_t> sids;
     for (int i = 0; i < 4; ++i) sids.push_back(s.open(5));
-    std::vector<uint64_t> tk;
+    // queued in one call: submitted one at a time, a later submission could
+    // meet the failed state the second micro-batch has already left
+    std::vector<uint64_t> tk(4);
+    std::vector<cm_request> qs(4, request(20, 8));
     std::string e;
-    for (int i = 0; i < 4; ++i) {
-        const cm_request q = request(20, 8);
-        uint64_t t = 0;
-        CHECK(s.core.submit(sids[i], &q, &t, &e) == CM_OK);
-        tk.push_back(t);
-    }
+    CHECK(s.core.submit_batch(4, sids.data(), qs.data(), tk.data(), &e) == CM_OK);
     check_result(s.core, tk[0], 8);
     std::vector<int32_t> idx(8);
     std::vector<float> val(8);
