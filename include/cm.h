@@ -51,6 +51,7 @@ extern "C" {
 #define CM_MAX_K 256         /* largest beam width of cm_topk_per_query */
 #define CM_STAGE_CHUNK 16    /* sets the stage split of CM_BF16 (see cm_eval_batch) */
 #define CM_STEP_MAX_QUERIES 256 /* queries per cm_step_run */
+#define CM_STATIC_MAX_STAGES 32768 /* stages per cm_eval_batch_static call */
 
 typedef int32_t cm_status;
 enum {
@@ -188,6 +189,24 @@ typedef struct {
 cm_status cm_eval_batch(const cm_model *model, cm_precision precision,
                         const cm_batch *batch, cm_workspace *ws, float *cost_out,
                         cm_stream stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cm_eval_batch without a workspace.  Same validation, kernels and results,
+ * bit for bit, as cm_eval_batch.  The per-stage hoisted rows (32 floats per
+ * stage) go to a scratch array that the library holds in device memory,
+ * one copy per device (4 MiB, kept until the process ends); its address is
+ * looked up when the first model is created on the device.  The call makes
+ * no allocation of any kind.
+ * Limit: the batch's n_stages summed over its queries must be at most
+ * CM_STATIC_MAX_STAGES (else CM_E2BIG, before any device work).
+ * Every call on one device uses that device's one scratch array, which keeps
+ * the last call's contents: calls that overlap on one device (different
+ * streams or threads) race and give wrong costs; serialise them.
+ * Errors: as cm_eval_batch (no workspace errors), CM_E2BIG above the limit,
+ * CM_EUNSUPPORTED for a device ordinal of 64 or more. */
+cm_status cm_eval_batch_static(const cm_model *model, cm_precision precision,
+                               const cm_batch *batch, float *cost_out, cm_stream stream);
 
 /* cm_eval_batch that also writes every stage's predicted cost (the v_s that
  * Sec. 5.2 sums over stages, as added to the stage sum):

@@ -18,7 +18,7 @@ from ._lib import (CM_BF16, CM_FP8, CM_FP32, CM_MAX_K, CM_N_PARAMS, CM_STAGE_CHU
 __all__ = [
     "CM_FP32", "CM_BF16", "CM_FP8", "CM_MAX_K", "CmError", "Model", "Workspace", "Batch",
     "cm_model_create", "cm_model_destroy", "cm_workspace_create", "cm_workspace_destroy",
-    "cm_eval_batch", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
+    "cm_eval_batch", "cm_eval_batch_static", "cm_hoist_stages", "cm_eval_hoisted", "cm_topk_per_query",
     "cm_version", "pack_queries", "Step", "cm_step_create", "cm_step_destroy", "cm_step_run",
     "cm_step_set_config", "cm_step_get_config", "cm_step_autotune", "cm_step_kernel_time",
     "cm_step_tuned_config",
@@ -178,6 +178,15 @@ def cm_eval_batch(model: Model, precision, batch: Batch, ws: Workspace, cost_out
     prec = PRECISIONS.get(precision, precision)
     check(lib().cm_eval_batch(model.handle, int(prec), ctypes.byref(batch.c), ws.handle,
                               _ptr(cost_out), _stream_handle(stream)))
+
+
+def cm_eval_batch_static(model: Model, precision, batch: Batch, cost_out, stream=None):
+    """cm_eval_batch without a workspace: the hoisted rows go to the library's
+    static device scratch (at most CM_STATIC_MAX_STAGES stages per call; calls
+    that overlap on one device race)."""
+    prec = PRECISIONS.get(precision, precision)
+    check(lib().cm_eval_batch_static(model.handle, int(prec), ctypes.byref(batch.c),
+                                     _ptr(cost_out), _stream_handle(stream)))
 
 
 def cm_eval_stages(model: Model, precision, batch: Batch, ws: Workspace, cost_out, stage_out,

@@ -21,6 +21,7 @@ CM_MAX_K = 256
 CM_N_PARAMS = 4184
 CM_STAGE_CHUNK = 16
 CM_STEP_MAX_QUERIES = 256
+CM_STATIC_MAX_STAGES = 32768
 
 # Every function the header declares, for the export check.
 EXPORTS = (
@@ -35,7 +36,7 @@ EXPORTS = (
     "cm_model_prepare_fp8", "cm_fp8_calibrate", "cm_fp8_encode",
     "cm_eval_stages", "cm_freeze_stages", "cm_penalize_known_bad", "cm_eval_indexed",
     "cm_sampler_create", "cm_sampler_destroy", "cm_sample_buckets",
-    "cm_server_set_step_config", "cm_server_get_step_config",
+    "cm_server_set_step_config", "cm_server_get_step_config", "cm_eval_batch_static",
     "cm_last_error", "cm_version",
 )
 
@@ -129,6 +130,7 @@ def lib():
         L.cm_workspace_create.argtypes = [ctypes.POINTER(cm_workspace_desc), ctypes.POINTER(vp)]
         L.cm_workspace_destroy.argtypes = [vp]
         L.cm_eval_batch.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp, vp]
+        L.cm_eval_batch_static.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp]
         L.cm_hoist_stages.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp]
         L.cm_eval_hoisted.argtypes = [vp, i32, ctypes.POINTER(cm_batch), vp, vp, vp, vp]
         L.cm_topk_per_query.argtypes = [vp, ctypes.POINTER(cm_batch), i32, vp, vp, vp, vp]
@@ -181,7 +183,7 @@ def lib():
                   "cm_fp8_calibrate", "cm_fp8_encode", "cm_eval_stages", "cm_freeze_stages",
                   "cm_penalize_known_bad", "cm_eval_indexed", "cm_sampler_create",
                   "cm_sampler_destroy", "cm_sample_buckets", "cm_server_set_step_config",
-                  "cm_server_get_step_config"):
+                  "cm_server_get_step_config", "cm_eval_batch_static"):
             getattr(L, f).restype = i32
         L.cm_last_error.restype = ctypes.c_char_p
         L.cm_last_error.argtypes = []

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -57,6 +58,38 @@ cm_status check_query_bytes(int64_t q, int64_t S, int64_t N, cm_precision prec, 
 namespace {
 
 using cm::fail;
+
+// Scratch of cm_eval_batch_static: the hoisted rows U[stages][32] of one
+// call, in a file-scope device array.  Every device the library runs on
+// holds its own copy until the process ends; calls on one device share it.
+__device__ __align__(256) float scratch[(size_t)CM_STATIC_MAX_STAGES * cm::H];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (in host code the array's name is not a device
+// address).
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+cm_status static_scratch(int dev, float **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= SCRATCH_DEVICES)
+        return fail(CM_EUNSUPPORTED, "device %d is beyond the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(CM_EDEVICE, "address of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CM_OK;
+}
 
 uint16_t f32_to_bf16(float f)  // round to nearest even
 {
@@ -336,6 +369,13 @@ cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model 
         delete M;
         return fail(CM_EDEVICE, "log table of the bf16 evaluator failed");
     }
+    // set-up of cm_eval_batch_static on this device
+    float *scr = nullptr;
+    if ((st = static_scratch(m.device, &scr)) != CM_OK) {
+        free_model(m);
+        delete M;
+        return st;
+    }
     *out = M;
     return CM_OK;
 }
@@ -574,6 +614,40 @@ cm_status cm_eval_batch(const cm_model *M, cm_precision prec, const cm_batch *b,
     hipStream_t s = (hipStream_t)stream;
     if ((st = hoist_impl(M, prec, b, W->w.d_U, s)) != CM_OK) return st;
     return eval_impl(M, prec, b, W->w.d_U, W->w, cost_out, nullptr, s);
+}
+
+cm_status cm_eval_batch_static(const cm_model *M, cm_precision prec, const cm_batch *b,
+                               float *cost_out, cm_stream stream)
+{
+    using namespace cm;
+    if (!M) return fail(CM_EINVAL, "model is NULL");
+    if (prec != CM_FP32 && prec != CM_BF16 && prec != CM_FP8)
+        return fail(CM_EUNSUPPORTED, "precision %d is not supported", prec);
+    // the descriptors first: no object is read before they have been checked
+    cm_status st = check_shape(b, prec, true);
+    if (st != CM_OK) return st;
+    int64_t stages = 0, cands = 0;
+    for (int32_t q = 0; q < b->n_queries; ++q) {
+        stages += b->queries[q].n_stages;
+        cands += b->queries[q].n_cands;
+    }
+    if (stages > CM_STATIC_MAX_STAGES)
+        return fail(CM_E2BIG, "batch has %lld stages, the static scratch holds %d",
+                    (long long)stages, CM_STATIC_MAX_STAGES);
+    if (prec == CM_FP8 && !M->m.d_fp8)
+        return fail(CM_EINVAL, "model has no FP8 form (cm_model_prepare_fp8)");
+    if ((st = check_device(M->m.device)) != CM_OK) return st;
+    if (cands == 0) return CM_OK;
+    if (!cost_out) return fail(CM_EINVAL, "cost_out is NULL");
+    if (!b->pipe || !b->sched || !b->terms)
+        return fail(CM_EINVAL, "batch pipe/sched/terms pointer is NULL");
+    if (!aligned(b->sched, 16) || !aligned(b->terms, 16) || !aligned(b->pipe, 4))
+        return fail(CM_EINVAL, "sched and terms must be 16-byte aligned");
+    float *U = nullptr;
+    if ((st = static_scratch(M->m.device, &U)) != CM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = hoist_impl(M, prec, b, U, s)) != CM_OK) return st;
+    return eval_impl(M, prec, b, U, Workspace{}, cost_out, nullptr, s);
 }
 
 cm_status cm_eval_stages(const cm_model *M, cm_precision prec, const cm_batch *b,

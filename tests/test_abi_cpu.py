@@ -237,3 +237,27 @@ def test_query_above_the_32_bit_offsets_is_rejected_before_device_work(cm):
     rc = L.cm_eval_indexed(fake, _lib.CM_BF16, ctypes.byref(b), base, 16, fake, base, None)
     assert rc == _lib.CM_E2BIG
     assert b"cost terms" in L.cm_last_error()
+
+
+def test_static_scratch_limits_are_checked_before_device_work(cm):
+    # cm_eval_batch_static keeps the hoisted rows in a fixed device array of
+    # CM_STATIC_MAX_STAGES stages: a batch with more stages, or a query above
+    # the 32-bit offsets, is rejected with CM_E2BIG before the model is read
+    # (fake handle: reading it would crash this process).
+    from paper_2012_07145_amd import _lib
+    L = _lib.lib()
+    fake = ctypes.c_void_p(16)
+    buf = (ctypes.c_float * 64)()
+    base = (ctypes.addressof(buf) + 15) // 16 * 16
+    n = _lib.CM_STATIC_MAX_STAGES // 100 + 1
+    q = (_lib.cm_query * n)(*[_lib.cm_query(100, 16, 0, 0, 0, 0) for _ in range(n)])
+    b = _lib.cm_batch(n, q, base, base, base)
+    assert n * 100 > _lib.CM_STATIC_MAX_STAGES
+    for prec in (_lib.CM_FP32, _lib.CM_BF16, _lib.CM_FP8):
+        assert L.cm_eval_batch_static(fake, prec, ctypes.byref(b), base, None) == _lib.CM_E2BIG
+        assert b"static scratch" in L.cm_last_error()
+    q1 = (_lib.cm_query * 1)(_lib.cm_query(64, 840_000, 0, 0, 0, 0))
+    b1 = _lib.cm_batch(1, q1, base, base, base)
+    assert L.cm_eval_batch_static(fake, _lib.CM_BF16, ctypes.byref(b1), base, None) == _lib.CM_E2BIG
+    assert b"schedule features" in L.cm_last_error()
+    assert L.cm_eval_batch_static(None, _lib.CM_BF16, ctypes.byref(b1), base, None) == _lib.CM_EINVAL
