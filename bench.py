@@ -260,9 +260,24 @@ def main():
     log(f"serving: {args.steps} steps, {cands} candidates in {wall * 1e3:.1f} ms "
         f"({st['micro_batches']} micro-batches)")
     launches = max(1, st["micro_batches"])
-    avg_us = st["kernel_us"] / launches
+    # The step kernel's device time over the timed region: the union of the
+    # launches' [first wave start, last wave end] intervals, from the kernel's
+    # own clock.  Consecutive micro-batches overlap on the device (the next
+    # one's workgroups start on compute units the previous one has left, and
+    # early in a run several are queued at once), so the mean of the
+    # launches' own spans counts that time twice; it is reported beside, as
+    # is the device time left idle between launches.
+    own_us = st["kernel_us"] / launches
+    if st["kernel_busy_launches"] == st["micro_batches"]:
+        avg_us = st["kernel_busy_us"] / launches
+        launch_time = ("union of the timed launches' intervals (first wave start to last wave "
+                       "end, the kernel's clock) per launch")
+    else:  # more launches than the server records: their own spans
+        avg_us = own_us
+        launch_time = "mean of the timed launches' own spans (first wave start to last wave end)"
+    idle_us = max(0.0, st["kernel_span_us"] / launches - avg_us)
     bytes_per_launch = st["kernel_bytes"] / launches
-    achieved = st["kernel_bytes"] / (st["kernel_us"] * 1e-6) / 1e9 if st["kernel_us"] else 0.0
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9 if avg_us else 0.0
     tr = traffic_record()
     read_roof = None
     if not args.no_read_probe:
@@ -557,7 +572,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],
-                     "kernel": "k_step_bf16", "avg_launch_us": avg_us,
+                     "kernel": "k_step_bf16", "avg_launch_us": avg_us, "launch_time": launch_time,
+                     "avg_launch_own_span_us": own_us,
+                     "frac_of_own_span": bytes_per_launch / (own_us * 1e3) / HBM_PEAK_GBS if own_us else None,
+                     "device_idle_us_per_launch": idle_us,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "launches": launches,
                      "measured_read_gbs": None if read_roof is None else read_roof[0],
                      "frac_of_measured_read": None if read_roof is None else achieved / read_roof[0]},

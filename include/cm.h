@@ -567,8 +567,16 @@ typedef struct {
     int32_t queue_depth;         /* queued now */
     int32_t in_flight;           /* admitted and unfinished now */
     int64_t arena_in_use, arena_high_water;
-    double kernel_us;            /* GPU time of the step kernels of completed micro-batches */
+    double kernel_us;            /* GPU time of the step kernels of completed micro-batches
+                                    (sum of each kernel's first-wave start to last-wave end) */
     int64_t kernel_bytes;        /* algorithmic bytes they read and wrote */
+    double kernel_span_us;       /* earliest start to latest end of those kernels (device
+                                    clock), gaps between them included */
+    double kernel_busy_us;       /* device time during which at least one of the most
+                                    recent kernel_busy_launches of them ran: the union of
+                                    their [start, end] intervals, so consecutive
+                                    micro-batches that overlap count once */
+    int64_t kernel_busy_launches;  /* min(micro-batches since reset, 4096) */
 } cm_server_stats;
 
 /* Create a server on the current device for `model`, which must outlive it.

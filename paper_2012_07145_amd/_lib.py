@@ -105,7 +105,8 @@ class cm_server_stats(ctypes.Structure):
                 ("max_us", ctypes.c_double), ("queue_depth", ctypes.c_int32),
                 ("in_flight", ctypes.c_int32), ("arena_in_use", ctypes.c_int64),
                 ("arena_high_water", ctypes.c_int64), ("kernel_us", ctypes.c_double),
-                ("kernel_bytes", ctypes.c_int64)]
+                ("kernel_bytes", ctypes.c_int64), ("kernel_span_us", ctypes.c_double),
+                ("kernel_busy_us", ctypes.c_double), ("kernel_busy_launches", ctypes.c_int64)]
 
 
 class CmError(RuntimeError):

@@ -186,8 +186,13 @@ struct StepHead {
     int32_t nrows;     // hoist rows over all queries
     int32_t k;         // beam width
     int32_t gpt;       // row-tile groups per task (1, 2 or 4)
-    int32_t pad[3];
+    int32_t pad;
+    // where the launch's (first start, last end) clock pair also goes, or
+    // null: host memory mapped for the device, so a server learns it without
+    // a copy
+    uint64_t *clk_out;
 };
+static_assert(sizeof(StepHead) == 32, "step head layout");
 
 // Control words of a step, zero between steps (the step kernel leaves them
 // zero when it ends): task queue head, exit count, per-query and per-tile
@@ -220,7 +225,10 @@ struct StepReq {
 // Queue one step over `n` queries on `st` (validated by the caller against
 // the step's capacities; n <= max_queries, sum N <= max_cands, sum S <=
 // max_stages when hoisting).
-cm_status step_launch(cm_step *S, const StepReq *r, int n, int k, bool hoist, hipStream_t st);
+// clk_out: optional device-visible address (host memory mapped for the
+// device) that also receives the launch's clock pair.
+cm_status step_launch(cm_step *S, const StepReq *r, int n, int k, bool hoist, hipStream_t st,
+                      uint64_t *clk_out = nullptr);
 // Capacities of a step.
 const cm_step_desc &step_caps(const cm_step *S);
 // Kernel-only GPU time (microseconds) of the step's most recent launch,

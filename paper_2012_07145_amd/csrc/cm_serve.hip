@@ -22,10 +22,11 @@ struct SlotDev {
     cm_step *step = nullptr;
     float *d_cost = nullptr;
     // the beams of a micro-batch, query j at word 2 j kb: kb indices, then
-    // kb values (one copy to the host covers the whole micro-batch)
-    uint32_t *d_beam = nullptr;
-    uint32_t *h_beam = nullptr;  // pinned
+    // kb values, written by the step kernel straight into pinned host memory
+    uint32_t *h_beam = nullptr;
     uint64_t *h_clk = nullptr;   // pinned: the step kernel's (first start, last end)
+    uint32_t *g_beam = nullptr;  // the two, as the device addresses them
+    uint64_t *g_clk = nullptr;
     hipEvent_t done = nullptr;
     int32_t kb = 0;
 };
@@ -64,8 +65,11 @@ float *session_U(cm_server &V, int32_t s)
 
 // The device side of the server for the host core: a micro-batch is one
 // persistent step (cm_step_run's kernels, hoisted rows from the session pool)
-// on the slot's stream, followed by one copy of its beams and of the kernel's
-// clock pair to pinned memory and the slot's completion event.
+// on the slot's stream, followed by the slot's completion event.  The step
+// kernel writes the micro-batch's beams and its clock pair straight into the
+// slot's pinned host buffers: a copy would run as a kernel of its own, which
+// cannot start while the next micro-batch's step kernel fills every compute
+// unit, so the batch would complete only when that one ends.
 class HipExecutor final : public cm::serve::Executor {
 public:
     explicit HipExecutor(cm_server *V) : V_(V) {}
@@ -84,8 +88,8 @@ public:
             q.u = session_U(*V_, w.session);
             q.pipe = nullptr;
             q.cost = sl.d_cost + off;
-            q.idx = reinterpret_cast<int32_t *>(sl.d_beam + (int64_t)j * 2 * kb);
-            q.val = reinterpret_cast<float *>(sl.d_beam + (int64_t)j * 2 * kb + kb);
+            q.idx = reinterpret_cast<int32_t *>(sl.g_beam + (int64_t)j * 2 * kb);
+            q.val = reinterpret_cast<float *>(sl.g_beam + (int64_t)j * 2 * kb + kb);
             q.sidx = V_->d_beam_idx + (int64_t)w.session * V_->cfg.k;
             q.sval = V_->d_beam_val + (int64_t)w.session * V_->cfg.k;
             q.S = w.S;
@@ -93,17 +97,12 @@ public:
             off += w.N;
         }
         sl.kb = kb;
-        if (cm::step_launch(sl.step, sr.data(), (int)sr.size(), kb, false, sl.st) != CM_OK) {
+        if (cm::step_launch(sl.step, sr.data(), (int)sr.size(), kb, false, sl.st, sl.g_clk) !=
+            CM_OK) {
             *err = cm_last_error();
             return false;
         }
-        const size_t nb = batch.size() * (size_t)kb;
-        hipError_t e = hipMemcpyAsync(sl.h_beam, sl.d_beam, 2 * nb * sizeof(uint32_t),
-                                      hipMemcpyDeviceToHost, sl.st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sl.h_clk, cm::step_clock(sl.step), 2 * sizeof(uint64_t),
-                               hipMemcpyDeviceToHost, sl.st);
-        if (e == hipSuccess) e = hipEventRecord(sl.done, sl.st);
+        const hipError_t e = hipEventRecord(sl.done, sl.st);
         if (e != hipSuccess) {
             *err = hipGetErrorString(e);
             return false;
@@ -132,6 +131,13 @@ public:
         return (double)(sl.h_clk[1] - sl.h_clk[0]) / cm::CLOCK_MHZ;
     }
 
+    void kernel_clock(int si, double *start_us, double *end_us) override
+    {
+        const SlotDev &sl = V_->slot[si];
+        *start_us = (double)sl.h_clk[0] / cm::CLOCK_MHZ;
+        *end_us = (double)sl.h_clk[1] / cm::CLOCK_MHZ;
+    }
+
 private:
     cm_server *V_;
 };
@@ -151,7 +157,6 @@ void free_server(cm_server *V)
         if (s.step) (void)cm_step_destroy(s.step);
         if (s.st) (void)hipStreamDestroy(s.st);
         if (s.d_cost) (void)hipFree(s.d_cost);
-        if (s.d_beam) (void)hipFree(s.d_beam);
         if (s.h_beam) (void)hipHostFree(s.h_beam);
         if (s.h_clk) (void)hipHostFree(s.h_clk);
         if (s.done) (void)hipEventDestroy(s.done);
@@ -222,9 +227,10 @@ cm_status cm_server_create(const cm_model *model, const cm_server_cfg *cfg, cm_s
         const size_t nb = (size_t)c.max_batch_queries * c.k;
         ok = ok && hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipMalloc((void **)&s.d_cost, (size_t)c.max_batch_cands * 4) == hipSuccess;
-        ok = ok && hipMalloc((void **)&s.d_beam, 2 * nb * 4) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&s.h_beam, 2 * nb * 4, 0) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&s.h_clk, 16, 0) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&s.h_beam, 2 * nb * 4, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&s.h_clk, 16, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+        ok = ok && hipHostGetDevicePointer((void **)&s.g_beam, s.h_beam, 0) == hipSuccess;
+        ok = ok && hipHostGetDevicePointer((void **)&s.g_clk, s.h_clk, 0) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess;
         if (ok) {
             const cm_step_desc sd{c.max_batch_queries, 1, c.max_batch_cands, c.k, 1};

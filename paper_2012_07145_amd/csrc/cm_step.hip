@@ -146,7 +146,7 @@ cm_status check_step_batch(const cm_step &S, const cm_batch *b, const float *U, 
 // longest stage part first; each query's outputs stay where its request
 // points.
 void fill_descriptors(const cm_step &S, Slot &sl, const cm::StepReq *r, int nq, int32_t k,
-                      bool hoist)
+                      bool hoist, uint64_t *clk_out)
 {
     using namespace cm;
     std::vector<int32_t> order(nq);
@@ -194,6 +194,7 @@ void fill_descriptors(const cm_step &S, Slot &sl, const cm::StepReq *r, int nq, 
     h->nrows = hoist ? (int32_t)row : 0;
     h->k = k;
     h->gpt = gpt;
+    h->clk_out = clk_out;
 }
 
 // The device work of one step on `st`: descriptor copy, hoist, step kernel.
@@ -243,13 +244,13 @@ cm_status get_exec(cm_step &S, Slot &sl, bool hoist, hipGraphExec_t *out)
 }
 
 cm_status launch_locked(cm_step &S, const cm::StepReq *r, int n, int32_t k, bool hoist,
-                        hipStream_t st)
+                        hipStream_t st, uint64_t *clk_out = nullptr)
 {
     if (n == 0) return CM_OK;
     Slot &sl = S.slot[S.next];
     if (sl.pending) CM_HIP(hipEventSynchronize(sl.done));  // its descriptors are still read
     sl.pending = false;
-    fill_descriptors(S, sl, r, n, k, hoist);
+    fill_descriptors(S, sl, r, n, k, hoist, clk_out);
     if (S.cfg.use_graph) {
         hipGraphExec_t ex = nullptr;
         cm_status rc = get_exec(S, sl, hoist, &ex);
@@ -389,10 +390,11 @@ void tune_save_locked()
 
 namespace cm {
 
-cm_status step_launch(cm_step *S, const StepReq *r, int n, int k, bool hoist, hipStream_t st)
+cm_status step_launch(cm_step *S, const StepReq *r, int n, int k, bool hoist, hipStream_t st,
+                      uint64_t *clk_out)
 {
     std::lock_guard<std::mutex> lk(S->mu);
-    return launch_locked(*S, r, n, k, hoist, st);
+    return launch_locked(*S, r, n, k, hoist, st, clk_out);
 }
 
 const cm_step_desc &step_caps(const cm_step *S) { return S->cap; }

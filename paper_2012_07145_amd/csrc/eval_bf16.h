@@ -401,15 +401,22 @@ typedef uint2 __attribute__((may_alias)) lds_u2;
 // its LDS block: three 16-byte-per-lane copies that each cover whole cache
 // lines (lane l's bytes land at 16 l), so every line is requested once.  Bytes
 // past the end of the buffer read as zero.
+// Cache policy of loads of data read exactly once (features and terms of a
+// materialized batch): non-temporal, so streaming them does not evict what
+// is reused (the log table, weights, hoisted rows, descriptors) from the
+// caches.
+constexpr int STREAM = 2;  // the nt bit of the buffer instructions' cache policy
+
 __device__ inline void dma_rows(uint4 *xsw, __amdgpu_buffer_rsrc_t xr, uint32_t row0, uint32_t soff,
                                 int lane)
 {
     const uint32_t vo = row0 + (uint32_t)lane * 16;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)xsw, 16, vo, soff, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)(xsw + 64), 16, vo + 1024, soff, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)xsw, 16, vo, soff, 0, STREAM);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)(xsw + 64), 16, vo + 1024, soff, 0,
+                                             STREAM);
     if (lane < 32)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (lds_void *)(xsw + 128), 16, vo + 2048, soff, 0,
-                                                 0);
+                                                 STREAM);
 }
 static_assert(TILE_ROWS * FS * 2 == 2560, "three copies of 1,024 + 1,024 + 512 bytes");
 
@@ -485,7 +492,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
         const lds_u2 *xs2 = reinterpret_cast<const lds_u2 *>(xsw);
         float4 tA, tB;
         auto load_t = [&](float4 &t) {
-            t = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, 0));
+            t = __builtin_bit_cast(float4,
+                                   __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, STREAM));
         };
         auto stage_in = [&](StageIn &in, const float4 &t) {
             // the stage's copy (and its terms, issued before it) have landed:

@@ -180,8 +180,16 @@ __device__ __forceinline__ void step_body(const StepHead *__restrict__ h,
         wait_stores();
         if (atomicAdd(&ctl[CTL_DONE], 1u) == gridDim.x - 1) {
             unsigned long long *out = reinterpret_cast<unsigned long long *>(ctl + CTL_CLKOUT);
-            store_shared(&out[0], atomicExch(&clk[0], ~0ull));
-            store_shared(&out[1], atomicExch(&clk[1], 0ull));
+            const unsigned long long c0 = atomicExch(&clk[0], ~0ull);
+            const unsigned long long c1 = atomicExch(&clk[1], 0ull);
+            store_shared(&out[0], c0);
+            store_shared(&out[1], c1);
+            if (h->clk_out) {
+                __hip_atomic_store(&h->clk_out[0], (uint64_t)c0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&h->clk_out[1], (uint64_t)c1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
             atomicExch(&ctl[CTL_NEXT], 0u);
             atomicExch(&ctl[CTL_DONE], 0u);
         }

@@ -7,7 +7,10 @@
 // flight per iteration, whole 128-byte lines per 8 lanes) and folds them into
 // one register; a word is written only if the fold hits a constant no
 // buffer of the probe's pattern produces, which keeps the loads without
-// adding traffic.
+// adding traffic.  The loads are non-temporal and the grid is 32 workgroups
+// of 4 waves per compute unit: on MI355X these read about 10% faster than
+// cached loads from 8 workgroups per compute unit (6.5 against 5.5-5.9 TB/s
+// over 4 GiB).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,20 +19,25 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_stream_read(const uint4 *__restrict__ p, uint64_t n,
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_read(const u32x4 *__restrict__ p, uint64_t n,
                                                      uint32_t *__restrict__ out)
 {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t acc = 0;
     for (; i + 3 * stride < n; i += 4 * stride) {
-        const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-        acc ^= (a.x + b.y) ^ (c.z + d.w) ^ (a.w + b.z) ^ (c.x + d.y) ^ (a.y ^ b.x ^ c.w ^ d.z) ^
-               (a.z ^ b.w ^ c.y ^ d.x);
+        const u32x4 a = __builtin_nontemporal_load(p + i);
+        const u32x4 b = __builtin_nontemporal_load(p + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(p + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(p + i + 3 * stride);
+        acc ^= (a[0] + b[1]) ^ (c[2] + d[3]) ^ (a[3] + b[2]) ^ (c[0] + d[1]) ^
+               (a[1] ^ b[0] ^ c[3] ^ d[2]) ^ (a[2] ^ b[3] ^ c[1] ^ d[0]);
     }
     for (; i < n; i += stride) {
-        const uint4 a = p[i];
-        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+        const u32x4 a = __builtin_nontemporal_load(p + i);
+        acc ^= a[0] ^ a[1] ^ a[2] ^ a[3];
     }
     if (acc == 0x9e3779b9u) out[blockIdx.x] = acc;
 }
@@ -50,9 +58,9 @@ int cm_probe_read_gbs(int64_t bytes, int32_t reps, double *median_gbs, double *b
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return -2;
-    uint4 *buf = nullptr;
+    u32x4 *buf = nullptr;
     uint32_t *out = nullptr;
-    const int grid = prop.multiProcessorCount * 8;
+    const int grid = prop.multiProcessorCount * 32;
     if (hipMalloc((void **)&buf, n * 16) != hipSuccess) return -3;
     if (hipMalloc((void **)&out, (size_t)grid * 4) != hipSuccess) {
         (void)hipFree(buf);

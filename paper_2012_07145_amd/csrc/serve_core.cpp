@@ -366,6 +366,24 @@ void Core::stats(cm_server_stats *o)
     o->arena_high_water = arena_high_;
     o->kernel_us = kernel_us_;
     o->kernel_bytes = kernel_bytes_;
+    o->kernel_span_us = kclk_first_ < 0 ? 0.0 : kclk_last_ - kclk_first_;
+    // union of the recorded kernels' [start, end] intervals
+    const size_t nk = (size_t)std::min<int64_t>(kring_n_, KRING);
+    std::vector<std::pair<double, double>> iv(kring_.begin(), kring_.begin() + (ptrdiff_t)nk);
+    std::sort(iv.begin(), iv.end());
+    double busy = 0, cs = 0, ce = 0;
+    for (size_t i = 0; i < iv.size(); ++i) {
+        if (i == 0 || iv[i].first > ce) {
+            busy += ce - cs;
+            cs = iv[i].first;
+            ce = iv[i].second;
+        } else if (iv[i].second > ce) {
+            ce = iv[i].second;
+        }
+    }
+    if (!iv.empty()) busy += ce - cs;
+    o->kernel_busy_us = busy;
+    o->kernel_busy_launches = (int64_t)nk;
 }
 
 void Core::reset_stats()
@@ -376,6 +394,9 @@ void Core::reset_stats()
     last_done_ = 0;
     kernel_us_ = 0;
     kernel_bytes_ = 0;
+    kclk_first_ = -1;
+    kclk_last_ = 0;
+    kring_n_ = 0;
     arena_high_ = arena_in_use_;
     lat_.clear();
 }
@@ -406,6 +427,12 @@ void Core::retire_locked(int si)
     if (ok) {
         kernel_us_ += ex_->kernel_us(si);
         kernel_bytes_ += sl.rows * (feature_bytes(cfg_.precision) + 32) + sl.cands * 4;
+        double ks = 0, ke = 0;
+        ex_->kernel_clock(si, &ks, &ke);
+        if (kclk_first_ < 0 || ks < kclk_first_) kclk_first_ = ks;
+        if (ke > kclk_last_) kclk_last_ = ke;
+        kring_[(size_t)(kring_n_ % KRING)] = {ks, ke};
+        ++kring_n_;
     }
     const double now = now_us();
     for (size_t j = 0; j < sl.tickets.size(); ++j) {

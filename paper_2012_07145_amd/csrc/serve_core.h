@@ -54,6 +54,9 @@ public:
     virtual const uint32_t *beam(int slot, size_t j) = 0;
     // GPU time (microseconds) of the slot's finished micro-batch's kernel.
     virtual double kernel_us(int slot) = 0;
+    // Device clock (microseconds from an arbitrary origin) of that kernel's
+    // first wave start and last wave end.
+    virtual void kernel_clock(int slot, double *start_us, double *end_us) = 0;
 };
 
 // Bytes a request takes from the arena while admitted.
@@ -159,6 +162,11 @@ private:
     // statistics
     int64_t n_sub_ = 0, n_done_ = 0, n_cancel_ = 0, n_cands_ = 0, n_rows_ = 0, n_mb_ = 0;
     double first_submit_ = -1, last_done_ = 0, kernel_us_ = 0;
+    double kclk_first_ = -1, kclk_last_ = 0;  // kernel start / end envelope (device clock)
+    // (start, end) of the most recent KRING kernels, in completion order
+    static constexpr int KRING = 4096;
+    std::vector<std::pair<double, double>> kring_ = std::vector<std::pair<double, double>>(KRING);
+    int64_t kring_n_ = 0;
     int64_t kernel_bytes_ = 0;
     std::vector<double> lat_;
 };

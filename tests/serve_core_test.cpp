@@ -96,6 +96,15 @@ public:
         return launches.size();
     }
     double kernel_us(int) override { return 1.0; }
+    // kernel i (in completion order, from 1) ran at device times
+    // [2i, 2i + width]: disjoint for width 1, overlapping its successor for 3
+    void kernel_clock(int, double *s, double *e) override
+    {
+        clk_ += 2.0;
+        *s = clk_;
+        *e = clk_ + width;
+    }
+    double clk_ = 0.0, width = 1.0;
 
 private:
     struct Slot {
@@ -197,6 +206,11 @@ void test_results_order_and_sessions()
     }
     CHECK(st.completed == 60 && st.submitted == 60 && st.in_flight == 0 && st.arena_in_use == 0);
     CHECK(st.micro_batches == (int64_t)s.ex.launches.size());
+    // the fake's kernels run at device times [2i, 2i + 1], i = 1 .. micro-batches
+    CHECK(st.kernel_us == (double)st.micro_batches);
+    CHECK(st.kernel_span_us == 2.0 * (double)(st.micro_batches - 1) + 1.0);
+    CHECK(st.kernel_busy_launches == st.micro_batches);
+    CHECK(st.kernel_busy_us == (double)st.micro_batches);  // disjoint unit intervals
     CHECK(st.p50_us <= st.p99_us && st.p99_us <= st.max_us);
 }
 
@@ -390,6 +404,32 @@ void test_concurrent_clients()
     CHECK(st.completed == 8 * 150 && st.in_flight == 0 && st.queue_depth == 0);
 }
 
+// The busy time is the union of the kernels' intervals: overlapping kernels
+// count once, and only the most recent 4096 are kept.
+void test_kernel_busy_time()
+{
+    Server s(config(2, 1 << 30, 64, 4, 8));
+    s.ex.width = 3.0;
+    const int32_t sid = s.open(4);
+    std::string e;
+    for (int r = 0; r < 5000; ++r) {
+        const cm_request q = request(16, 1);
+        uint64_t t = 0;
+        CHECK(s.core.submit(sid, &q, &t, &e) == CM_OK);
+        check_result(s.core, t, 1);
+    }
+    cm_server_stats st;
+    s.core.stats(&st);
+    CHECK(st.micro_batches == 5000);
+    CHECK(st.kernel_us == 5000.0);  // the fake reports 1 us per kernel
+    CHECK(st.kernel_span_us == 2.0 * 4999 + 3.0);
+    CHECK(st.kernel_busy_launches == 4096);
+    CHECK(st.kernel_busy_us == 2.0 * 4095 + 3.0);  // [2i, 2i + 3] for the last 4096 i
+    s.core.reset_stats();
+    s.core.stats(&st);
+    CHECK(st.kernel_busy_launches == 0 && st.kernel_busy_us == 0.0 && st.kernel_span_us == 0.0);
+}
+
 void test_stop_drains_the_queue()
 {
     std::vector<uint64_t> tk;
@@ -425,6 +465,7 @@ int main()
     test_forced_launch_failure();
     test_failed_micro_batch();
     test_concurrent_clients();
+    test_kernel_busy_time();
     test_stop_drains_the_queue();
     std::printf("serve core: all checks passed\n");
     return 0;
