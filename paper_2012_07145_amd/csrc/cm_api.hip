@@ -303,40 +303,39 @@ cm_status cm_model_create(const cm_model_desc *d, const float *params, cm_model 
     }
     Bf16Pack pk;
     std::memset(&pk, 0, sizeof pk);
-    for (int st = 0; st < 3; ++st)
+    // operands of the 16x16x32 bf16 matrix core: lane l holds row l % 16 and
+    // k-slots 8g .. 8g+7, g = l / 16
+    for (int hh = 0; hh < 2; ++hh)
         for (int lane = 0; lane < 64; ++lane) {
-            uint16_t hi[8], lo[8];
-            for (int j = 0; j < 8; ++j) {
-                // k-slot (step st, lane half hf, element j) -> schedule feature.
-                // Step 2 holds four features per lane half: its activation
-                // operand carries their high parts in slots 0..3 and their low
-                // parts in slots 4..7, so one product with the high weights
-                // repeated in slots 4..7 takes hi*hi + hi*lo and one with the
-                // low weights (zero in 4..7) takes lo*hi.
-                const int mrow = lane & 31, hf = lane >> 5;
-                if (st < 2) {
-                    split_bf16(Wf[mrow][st * 16 + hf * 8 + j], hi[j], lo[j]);
-                } else {
-                    uint16_t unused;
-                    split_bf16(Wf[mrow][32 + hf * 4 + (j & 3)], hi[j], j < 4 ? lo[j] : unused);
-                    if (j >= 4) lo[j] = 0;
-                }
-            }
-            std::memcpy(&pk.a1[0][st][lane], hi, 16);
-            std::memcpy(&pk.a1[1][st][lane], lo, 16);
+            const int row = 16 * hh + (lane & 15), g = lane >> 4;  // hidden unit
+            uint16_t wh[8], wl[8];
+            for (int j = 0; j < 8; ++j) split_bf16(Wf[row][8 * g + j], wh[j], wl[j]);
+            // last block: features a = 32 + 2g and b = a + 1 against the
+            // operand (hi a, hi b, lo a, lo b, hi a, hi b, lo a, lo b)
+            uint16_t ha, la, hb, lb;
+            split_bf16(Wf[row][32 + 2 * g], ha, la);
+            split_bf16(Wf[row][33 + 2 * g], hb, lb);
+            const uint16_t wx[8] = {ha, hb, ha, hb, la, lb, 0, 0};
+            std::memcpy(&pk.a1[hh][0][lane], wh, 16);
+            std::memcpy(&pk.a1[hh][1][lane], wl, 16);
+            std::memcpy(&pk.a1[hh][2][lane], wx, 16);
         }
-    for (int t = 0; t < 2; ++t)
-        for (int lane = 0; lane < 64; ++lane) {
-            uint16_t hi[8], lo[8];
-            const int mo = lane & 31, hf = lane >> 5;
-            for (int j = 0; j < 8; ++j) {
-                const int r = t * 8 + j;                      // output register of layer 1
-                const int p = (r >> 2) * 8 + hf * 4 + (r & 3);  // its hidden unit
-                split_bf16(mo < C ? (double)W2[mo * H + p] : 0.0, hi[j], lo[j]);
-            }
-            std::memcpy(&pk.a2[0][t][lane], hi, 16);
-            std::memcpy(&pk.a2[1][t][lane], lo, 16);
+    for (int lane = 0; lane < 64; ++lane) {
+        // row m: coefficient m & 7, high weights for m < 8, low ones above;
+        // slot j: hidden unit 4g + j (j < 4) or 16 + 4g + j - 4, the order of
+        // the first layer's output registers
+        const int m = lane & 15, g = lane >> 4;
+        uint16_t ws[8], wh[8];
+        for (int j = 0; j < 8; ++j) {
+            const int p = j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
+            uint16_t hi, lo;
+            split_bf16((double)W2[(m & 7) * H + p], hi, lo);
+            ws[j] = m < 8 ? hi : lo;
+            wh[j] = m < 8 ? hi : 0;
         }
+        std::memcpy(&pk.a2[0][lane], ws, 16);
+        std::memcpy(&pk.a2[1][lane], wh, 16);
+    }
     for (int mo = 0; mo < C; ++mo) pk.b2[mo] = params[OFF_B2 + mo];
 
     m.h_params = new (std::nothrow) float[N_PARAMS];

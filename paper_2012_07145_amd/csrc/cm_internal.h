@@ -51,8 +51,10 @@ constexpr uint32_t LOG_BASE = 0x3380u;
 constexpr int LOG_N = 8192;
 
 struct Bf16Pack {
-    uint4 a1[2][3][64];  // folded first layer (32 hidden x 48 padded features)
-    uint4 a2[2][2][64];  // coefficient layer (32 padded outputs x 32 hidden)
+    // 16x16x32 operands (lane l: row l % 16, k-slots 8 (l / 16) .. +7)
+    uint4 a1[2][3][64];  // folded first layer per hidden half: high and low
+                         // weights of features 0..31, last-block operand
+    uint4 a2[2][64];     // coefficient layer: rows [W_2 high; W_2 low] and [W_2 high; 0]
     float b2[8];
     float pad[4];
     // (high bf16 | low bf16 << 16) of log2(1 + x) for code LOG_BASE + i,

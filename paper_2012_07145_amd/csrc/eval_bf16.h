@@ -5,30 +5,39 @@
 // Work unit = one wavefront x (32 candidates of one query) x (one part of the
 // query's stages; stage_parts() splits them into 1, 2, 4 or 8 contiguous
 // parts by stage count alone).  A group of 8 waves holds every part of its
-// row tiles.  Per stage the wave
+// row tiles.  The matrix work runs on the 16x16x32 bf16 matrix core, whose
+// operands give lane l the row or column l mod 16 and the k-slots
+// 8 (l / 16) .. +7, and whose output gives lane l column l mod 16, rows
+// 4 (l / 16) .. +3.  The wave's 32 candidates are two halves of 16 (columns).
+// Per stage the wave
 //   1. loads the 32 candidates' bf16 schedule features (stage-major rows of
-//      80 bytes; each row is split over two lanes, 40 bytes each) and their
-//      float32 cost terms, one stage ahead of the arithmetic: the features
-//      as three whole-line copies from memory into the wave's LDS block
-//      (read into registers when the stage starts), the terms into
-//      registers (memoized rows, which are gathered by number, are loaded
-//      straight into registers);
+//      80 bytes) and their float32 cost terms, one stage ahead of the
+//      arithmetic: the features as three whole-line copies from memory into
+//      the wave's LDS block (read into registers when the stage starts:
+//      lane l takes features 8g .. 8g+7 and 32+2g, 33+2g, g = l / 16, of
+//      candidates l mod 16 and 16 + l mod 16), the terms into registers
+//      (memoized rows, which are gathered by number, are loaded straight into
+//      registers);
 //   2. takes log2(1 + x) in float32 (ln 2 is folded into the weights, so the
 //      layer sees log1p(x)) and splits it into high and low bf16 parts: by
 //      lookup in an LDS table of both parts per feature code, or, for a
 //      stage whose wave holds a code outside the table, by computing it;
-//   3. runs the first layer as D[hidden][cand] = Wf . X^T on the 32x32x16 bf16
-//      matrix core: Wf = W_1[:, 24:] W_s is the schedule embedding folded into
-//      the first layer (no activation sits between them), the accumulator
-//      starts from the hoisted per-stage vector U[s] (algorithm embedding,
-//      biases), and each product is hi*hi + lo*hi + hi*lo;
+//   3. runs the first layer as D[hidden][cand] = Wf . X^T in four 16x16 tiles
+//      (two hidden halves x two candidate halves): Wf = W_1[:, 24:] W_s is the
+//      schedule embedding folded into the first layer (no activation sits
+//      between them), the accumulators start from the hoisted per-stage
+//      vector U[s] (algorithm embedding, biases), and each product is
+//      hi*hi + lo*hi + hi*lo;
 //   4. applies the ReLU, splits the hidden activations the same way and runs
-//      the coefficient layer (8 outputs padded to 32) on the matrix core; the
-//      hidden order is permuted in the packed weights so that the first
-//      layer's output registers are already the second layer's operands;
-//   5. applies the ReLU to the 8 coefficients, dots them with the 8 cost
-//      terms (two lanes hold four each and exchange halves) and adds the
-//      stage prediction to a Kahan-compensated float32 sum (App. B).
+//      the coefficient layer per candidate half as one 16-row product: rows
+//      0..7 take the 8 coefficients against the high weights, rows 8..15
+//      against the low weights, so both weight parts share one instruction;
+//      the two hidden tiles of a candidate half are already the layer's
+//      32-slot operand (the packed weights follow their order);
+//   5. adds the two weight parts of each coefficient across lane halves,
+//      applies the ReLU, dots the 8 coefficients with the 8 cost terms (two
+//      lanes hold four each and exchange halves) and adds the stage
+//      prediction to a Kahan-compensated float32 sum (App. B).
 // Each part's (sum, compensation) pair goes through LDS and the first wave of
 // the tile combines the parts in ascending order, so the result of a
 // candidate depends only on its query, never on the batch, the launch shape
@@ -45,7 +54,7 @@ constexpr int USTAGE = 16;  // hoisted rows staged in LDS per refill
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint32_t pack_bf16x2(float a, float b)
 {
@@ -104,19 +113,22 @@ __device__ inline void log_split(uint4 raw, bf16x8 &hi, bf16x8 &lo, const Pairs 
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
-// 4 raw bf16 features (plus 4 zero slots) -> high/low operands.
-__device__ inline void log_split4(uint2 raw, bf16x8 &hi, bf16x8 &lo, const Pairs &k)
+// The last-block operand of a word of two raw bf16 features a, b: slots
+// (hi a, hi b, lo a, lo b, hi a, hi b, lo a, lo b).  Its packed weights are
+// (Wh a, Wh b, Wh a, Wh b, Wl a, Wl b, 0, 0): one product takes
+// hi*hi + lo*hi + hi*lo of both features.
+__device__ inline bf16x8 last_operand(uint32_t h, uint32_t l)
 {
-    uint32_t w[2] = {raw.x, raw.y};
-    uint32_t h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-        const float y0 = __builtin_amdgcn_logf(dot(w[d], k.one_lo, 1.0f));
-        const float y1 = __builtin_amdgcn_logf(dot(w[d], k.one_hi, 1.0f));
-        split2(y0, y1, h[d], l[d], k);
-    }
-    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
-    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+    return __builtin_bit_cast(bf16x8, make_uint4(h, l, h, l));
+}
+
+__device__ inline bf16x8 log_last(uint32_t raw, const Pairs &k)
+{
+    const float y0 = __builtin_amdgcn_logf(dot(raw, k.one_lo, 1.0f));
+    const float y1 = __builtin_amdgcn_logf(dot(raw, k.one_hi, 1.0f));
+    uint32_t h, l;
+    split2(y0, y1, h, l, k);
+    return last_operand(h, l);
 }
 
 // ---- the log transform by table lookup ----
@@ -171,14 +183,11 @@ __device__ inline void tab_split(const uint32_t *tab, uint32_t i0, uint32_t i1, 
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
-__device__ inline void tab_split4(const uint32_t *tab, uint32_t i0, uint32_t i1, bf16x8 &hi,
-                                  bf16x8 &lo)
+__device__ inline bf16x8 tab_last(const uint32_t *tab, uint32_t ix)
 {
-    uint32_t h[2], l[2];
-    tab_pair(tab, i0, h[0], l[0]);
-    tab_pair(tab, i1, h[1], l[1]);
-    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], 0u, 0u));
-    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], 0u, 0u));
+    uint32_t h, l;
+    tab_pair(tab, ix, h, l);
+    return last_operand(h, l);
 }
 
 // Copy the table into LDS (every thread of the workgroup; the caller
@@ -205,9 +214,9 @@ __device__ inline void kahan_add(float &s, float &c, float v)
     s = t;
 }
 
-__device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c)
+__device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // Sum of a value held by lane l and lane l ^ 32, identical in both lanes.
@@ -218,21 +227,32 @@ __device__ inline float add_halves(float v)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// One stage's operands for one lane: features 16*st + 8*hf .. +8 for st = 0, 1,
-// features 32 + 4*hf .. +4, and cost terms 4*hf .. +4.
+// Sum of a value held by lane l and lane l ^ 16, identical in both lanes.
+__device__ inline float add_pairs16(float v)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// One stage's operands for one lane (g = lane / 16): x0, x1 = features
+// 8g .. 8g+7 of candidates lane % 16 and 16 + lane % 16; x2 = features 32+2g
+// and 33+2g of the same two candidates; t = cost terms 4q .. 4q+3
+// (q = (lane / 16) % 2) of the lane's own candidate 16 (lane / 32) + lane % 16.
 struct StageIn {
     uint4 x0, x1;
     uint2 x2;
     float4 t;
-    bool bad;  // memoized rows: the stage's row number is outside the table
+    bool bad;  // memoized rows: the row number of the lane's own candidate is outside the table
 };
 
 // This lane's part of a stage's hoisted row (the first layer's accumulator
-// seed): hidden units g*8 + hf*4 .. +4 for g = 0..3, from the wave's LDS slice.
-__device__ inline void read_u(float4 (&u)[4], const float4 *us, int hf)
+// seed): hidden units 4g .. 4g+3 and 16+4g .. 16+4g+3, from the wave's LDS
+// slice.
+__device__ inline void read_u(float4 (&u)[2], const float4 *us, int g)
 {
-#pragma unroll
-    for (int g = 0; g < 4; ++g) u[g] = us[g * 2 + hf];
+    u[0] = us[g];
+    u[1] = us[4 + g];
 }
 
 // Buffer descriptor over n bytes at p (raw, untyped dword access; loads at
@@ -246,20 +266,26 @@ __device__ inline __amdgpu_buffer_rsrc_t buffer_over(const void *p, uint32_t n)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-// One stage's loads: xsoff, tsoff = byte offsets of the stage's rows
-// (uniform); xo, x2o, to = this lane's byte offsets inside the stage.
+// One stage's loads from memoized rows: xsoff, tsoff = byte offsets of the
+// stage's rows (uniform); xo0, xo1 = byte offsets of the two candidates' rows,
+// to = of this lane's terms inside the stage; g = lane / 16.
 __device__ inline void load_stage(StageIn &in, __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t tr,
-                                  uint32_t xsoff, uint32_t tsoff, uint32_t xo, uint32_t x2o,
-                                  uint32_t to)
+                                  uint32_t xsoff, uint32_t tsoff, uint32_t xo0, uint32_t xo1,
+                                  int g, uint32_t to)
 {
-    in.x0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo, xsoff, 0));
-    in.x1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo + 32, xsoff, 0));
-    in.x2 = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(xr, x2o, xsoff, 0));
+    in.x0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo0 + 16 * g, xsoff, 0));
+    in.x1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo1 + 16 * g, xsoff, 0));
+    in.x2.x = __builtin_amdgcn_raw_buffer_load_b32(xr, xo0 + 64 + 4 * g, xsoff, 0);
+    in.x2.y = __builtin_amdgcn_raw_buffer_load_b32(xr, xo1 + 64 + 4 * g, xsoff, 0);
     in.t = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(tr, to, tsoff, 0));
 }
 
+// Packed weights held by a lane for the whole wave: per hidden half hh, the
+// first layer's high and low weights of features 0..31 and its last-block
+// operand; the coefficient layer's [high; low] and [high; 0] operands; the
+// coefficient biases 4q .. 4q+3.
 struct Weights {
-    bf16x8 A1h[3], A1l[3], A2h[2], A2l[2];
+    bf16x8 A1h[2], A1l[2], A1x[2], A2s, A2h;
     float b2v[4];
 };
 
@@ -272,24 +298,37 @@ __device__ inline void refill_u(float4 *ur, const float4 *ug, int s, int n, int 
     __builtin_amdgcn_wave_barrier();
 }
 
+// One candidate half's coefficient layer: t0, t1 = its first-layer tiles
+// (hidden 4g .. 4g+3 and 16+4g .. 16+4g+3 of the lane's column), ReLU, split
+// into high and low bf16 parts, then rows 0..7 = W_2,hi (h_hi + h_lo) and
+// rows 8..15 = W_2,lo h_hi.
+__device__ __forceinline__ f32x4 coef_layer(const f32x4 &t0, const f32x4 &t1, const Weights &w,
+                                            const Pairs &kp)
+{
+    uint32_t hh[4], hl[4];
+    split2(relu(t0[0]), relu(t0[1]), hh[0], hl[0], kp);
+    split2(relu(t0[2]), relu(t0[3]), hh[1], hl[1], kp);
+    split2(relu(t1[0]), relu(t1[1]), hh[2], hl[2], kp);
+    split2(relu(t1[2]), relu(t1[3]), hh[3], hl[3], kp);
+    const bf16x8 Hh = __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
+    const bf16x8 Hl = __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    return mfma(w.A2h, Hl, mfma(w.A2s, Hh, z));
+}
+
 // One stage of 32 candidates: both dense layers on the matrix cores, the
 // coefficient dot product with the cost terms, and the compensated sum.
-// Returns the stage's cost (in every lane of the candidate).
-__device__ __forceinline__ float stage_math(const StageIn &in, const float4 (&u)[4], int hf,
+// g = lane / 16, upper = lane >= 32.  Returns the stage's cost (in both lanes
+// of the lane's own candidate).
+__device__ __forceinline__ float stage_math(const StageIn &in, const float4 (&u)[2], bool upper,
                                             const Weights &w, const Pairs &kp,
                                             const uint32_t *tab, float &sum, float &comp)
 {
-    // first layer: accumulator starts from U[s]; register g*4+j holds
-    // hidden unit g*8 + hf*4 + j
-    f32x16 acc;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const float4 u4 = u[g];
-        acc[g * 4 + 0] = u4.x;
-        acc[g * 4 + 1] = u4.y;
-        acc[g * 4 + 2] = u4.z;
-        acc[g * 4 + 3] = u4.w;
-    }
+    // first layer: tile t<hh><c> = hidden 16hh + 4g .. +3 of candidate
+    // 16c + lane % 16, seeded with U[s]
+    const f32x4 u0 = {u[0].x, u[0].y, u[0].z, u[0].w};
+    const f32x4 u1 = {u[1].x, u[1].y, u[1].z, u[1].w};
+    f32x4 t00 = u0, t10 = u1, t01 = u0, t11 = u1;
     // table indices of the stage's 20 codes, and whether every code of the
     // wave is in the table (one uniform branch per stage)
     const uint32_t ix[10] = {tab_index(in.x0.x), tab_index(in.x0.y), tab_index(in.x0.z),
@@ -299,54 +338,65 @@ __device__ __forceinline__ float stage_math(const StageIn &in, const float4 (&u)
     const uint32_t all = ix[0] | ix[1] | ix[2] | ix[3] | ix[4] | ix[5] | ix[6] | ix[7] | ix[8] |
                          ix[9];
     const bool fast = __builtin_amdgcn_ballot_w64((all & TAB_OUT) != 0u) == 0;
-    bf16x8 bh, bl;
-    if (fast) tab_split(tab, ix[0], ix[1], ix[2], ix[3], bh, bl);
-    else log_split(in.x0, bh, bl, kp);
-    acc = mfma(w.A1h[0], bh, acc);
-    acc = mfma(w.A1l[0], bh, acc);
-    acc = mfma(w.A1h[0], bl, acc);
-    if (fast) tab_split(tab, ix[4], ix[5], ix[6], ix[7], bh, bl);
-    else log_split(in.x1, bh, bl, kp);
-    acc = mfma(w.A1h[1], bh, acc);
-    acc = mfma(w.A1l[1], bh, acc);
-    acc = mfma(w.A1h[1], bl, acc);
-    if (fast) tab_split4(tab, ix[8], ix[9], bh, bl);
-    else log_split4(in.x2, bh, bl, kp);
-    // the last four features per lane half: high parts in slots 0..3, low
-    // parts in 4..7 (the packed weights repeat the high weights in 4..7)
-    {
-        const uint4 h4 = __builtin_bit_cast(uint4, bh), l4 = __builtin_bit_cast(uint4, bl);
-        const bf16x8 b2 = __builtin_bit_cast(bf16x8, make_uint4(h4.x, h4.y, l4.x, l4.y));
-        acc = mfma(w.A1h[2], b2, acc);
-        acc = mfma(w.A1l[2], b2, acc);
+    bf16x8 bh, bl, bx;
+    // candidates 0..15 (both hidden halves share the operands)
+    if (fast) {
+        tab_split(tab, ix[0], ix[1], ix[2], ix[3], bh, bl);
+        bx = tab_last(tab, ix[8]);
+    } else {
+        log_split(in.x0, bh, bl, kp);
+        bx = log_last(in.x2.x, kp);
     }
-
-    const bool invalid = acc[0] != acc[0];  // NaN: an input outside log1p's domain
-
-    // coefficient layer (output registers 0..3 are the 8 real outputs); its
-    // bias is added after the products
-    f32x16 acc2;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        uint32_t hh[4], hl[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d)
-            split2(relu(acc[t * 8 + 2 * d]), relu(acc[t * 8 + 2 * d + 1]), hh[d], hl[d], kp);
-        const bf16x8 Hh = __builtin_bit_cast(bf16x8, make_uint4(hh[0], hh[1], hh[2], hh[3]));
-        const bf16x8 Hl = __builtin_bit_cast(bf16x8, make_uint4(hl[0], hl[1], hl[2], hl[3]));
-        acc2 = mfma(w.A2h[t], Hh, acc2);
-        acc2 = mfma(w.A2l[t], Hh, acc2);
-        acc2 = mfma(w.A2h[t], Hl, acc2);
+    t00 = mfma(w.A1h[0], bh, t00);
+    t10 = mfma(w.A1h[1], bh, t10);
+    t00 = mfma(w.A1l[0], bh, t00);
+    t10 = mfma(w.A1l[1], bh, t10);
+    t00 = mfma(w.A1h[0], bl, t00);
+    t10 = mfma(w.A1h[1], bl, t10);
+    t00 = mfma(w.A1x[0], bx, t00);
+    t10 = mfma(w.A1x[1], bx, t10);
+    // candidates 16..31
+    if (fast) {
+        tab_split(tab, ix[4], ix[5], ix[6], ix[7], bh, bl);
+        bx = tab_last(tab, ix[9]);
+    } else {
+        log_split(in.x1, bh, bl, kp);
+        bx = log_last(in.x2.y, kp);
     }
-    // lanes hf=0 hold coefficients 0..3 of their candidate, hf=1 hold 4..7
-    float v = relu(acc2[0] + w.b2v[0]) * in.t.x;
-    v = fmaf(relu(acc2[1] + w.b2v[1]), in.t.y, v);
-    v = fmaf(relu(acc2[2] + w.b2v[2]), in.t.z, v);
-    v = fmaf(relu(acc2[3] + w.b2v[3]), in.t.w, v);
+    t01 = mfma(w.A1h[0], bh, t01);
+    t11 = mfma(w.A1h[1], bh, t11);
+    t01 = mfma(w.A1l[0], bh, t01);
+    t11 = mfma(w.A1l[1], bh, t11);
+    t01 = mfma(w.A1h[0], bl, t01);
+    t11 = mfma(w.A1h[1], bl, t11);
+    t01 = mfma(w.A1x[0], bx, t01);
+    t11 = mfma(w.A1x[1], bx, t11);
+
+    // NaN: an input outside log1p's domain (the lane's own candidate is in
+    // the first tile of its half)
+    const float pre = upper ? t01[0] : t00[0];
+    const bool invalid = pre != pre;
+
+    const f32x4 d0 = coef_layer(t00, t10, w, kp);
+    const f32x4 d1 = coef_layer(t01, t11, w, kp);
+    // rows 4g .. 4g+3 of d_c: lanes 0..31 hold the high-weight parts of
+    // coefficients, lanes 32..63 the low-weight parts of the same ones.  The
+    // swap gathers, in lanes 0..31, candidate half 0 and in lanes 32..63 half
+    // 1, with the high parts in its first result and the low parts in its
+    // second: lane l then holds coefficients 4q .. 4q+3 of its own candidate.
+    float cf[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(d0[j]),
+                                                        __float_as_uint(d1[j]), false, false);
+        cf[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float v = relu(cf[0] + w.b2v[0]) * in.t.x;
+    v = fmaf(relu(cf[1] + w.b2v[1]), in.t.y, v);
+    v = fmaf(relu(cf[2] + w.b2v[2]), in.t.z, v);
+    v = fmaf(relu(cf[3] + w.b2v[3]), in.t.w, v);
     if (invalid || in.bad) v = __builtin_nanf("");
-    const float vs = add_halves(v);
+    const float vs = add_pairs16(v);
     kahan_add(sum, comp, vs);
     return vs;
 }
@@ -355,19 +405,17 @@ __device__ __forceinline__ float stage_math(const StageIn &in, const float4 (&u)
 __device__ inline Weights load_weights(const Bf16Pack *__restrict__ pk, int lane)
 {
     Weights w;
-    const int hf = lane >> 5;
+    const int q = (lane >> 4) & 1;
 #pragma unroll
-    for (int st = 0; st < 3; ++st) {
-        w.A1h[st] = __builtin_bit_cast(bf16x8, pk->a1[0][st][lane]);
-        w.A1l[st] = __builtin_bit_cast(bf16x8, pk->a1[1][st][lane]);
+    for (int hh = 0; hh < 2; ++hh) {
+        w.A1h[hh] = __builtin_bit_cast(bf16x8, pk->a1[hh][0][lane]);
+        w.A1l[hh] = __builtin_bit_cast(bf16x8, pk->a1[hh][1][lane]);
+        w.A1x[hh] = __builtin_bit_cast(bf16x8, pk->a1[hh][2][lane]);
     }
+    w.A2s = __builtin_bit_cast(bf16x8, pk->a2[0][lane]);
+    w.A2h = __builtin_bit_cast(bf16x8, pk->a2[1][lane]);
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        w.A2h[t] = __builtin_bit_cast(bf16x8, pk->a2[0][t][lane]);
-        w.A2l[t] = __builtin_bit_cast(bf16x8, pk->a2[1][t][lane]);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) w.b2v[r] = pk->b2[hf * 4 + r];
+    for (int r = 0; r < 4; ++r) w.b2v[r] = pk->b2[q * 4 + r];
     return w;
 }
 
@@ -395,7 +443,7 @@ struct GroupShared {
 typedef __attribute__((address_space(3))) void lds_void;
 // Views of a copy block in other element types (may_alias: no type-based
 // alias analysis between them and the block's own type).
-typedef uint2 __attribute__((may_alias)) lds_u2;
+typedef uint32_t __attribute__((may_alias)) lds_u1;
 
 // The 2,560 contiguous bytes of a wave's 32 feature rows of one stage into
 // its LDS block: three 16-byte-per-lane copies that each cover whole cache
@@ -436,8 +484,15 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     const int P = Q.P;
     const int tile = group * (EVAL_WAVES / P) + wave / P;
     const int part = wave % P;
-    const int n = lane & 31;
-    const int hf = lane >> 5;
+    // lane l: g = l / 16 selects the features and hoisted units it feeds to
+    // the matrix core for candidates r = l % 16 and 16 + r; its own candidate
+    // (terms, sum, result) is n = 16 (l / 32) + r, of which it holds
+    // coefficients 4q .. 4q+3; the lane with q = 0 stores
+    const int g = lane >> 4;
+    const int r = lane & 15;
+    const bool upper = lane >= 32;
+    const int q = g & 1;
+    const int n = (upper ? 16 : 0) + r;
     const int i = tile * TILE_ROWS + n;
     const bool valid = i < Q.N;
     // rows past the end of the query compute on other bytes (the last row's
@@ -461,22 +516,23 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     const __amdgpu_buffer_rsrc_t tr = buffer_over(Q.t, tstep * (uint32_t)Q.S);
     uint32_t xsoff = (uint32_t)s0 * xstep;
     uint32_t tsoff = (uint32_t)s0 * tstep;
-    uint32_t xo = (uint32_t)ic * (FS * 2) + hf * 16;      // features 8*hf .. +8, +16 ..
-    uint32_t x2o = (uint32_t)ic * (FS * 2) + 64 + hf * 8;  // features 32 + 4*hf .. +4
-    const uint32_t to = (uint32_t)ic * (C * 4) + hf * 16;
-    // memoized rows: the row number of the stage loaded next, read one stage
-    // ahead of its feature loads; a row outside the table reads past the
-    // buffer's end (zeros) and is flagged
-    int32_t rnext = 0;
+    const uint32_t to = (uint32_t)ic * (C * 4) + q * 16;
+    // memoized rows: the row numbers of the stage loaded next (candidates r
+    // and 16 + r), read one stage ahead of their feature loads; a row outside
+    // the table reads past the buffer's end (zeros) and flags the lane's own
+    // candidate when it is that one
+    const int ic0 = min(tile * TILE_ROWS + r, Q.N - 1);
+    const int ic1 = min(tile * TILE_ROWS + 16 + r, Q.N - 1);
+    uint32_t xo0 = 0, xo1 = 0;
+    int32_t rnext0 = 0, rnext1 = 0;
     bool bad = false;
-    auto point_at = [&](int32_t r) {
-        const bool ok = (uint32_t)r < Q.rows;
-        const uint32_t ro = ok ? (uint32_t)r * (FS * 2) : xbytes;
-        xo = ro + hf * 16;
-        x2o = ro + 64 + hf * 8;
-        bad = !ok;
+    auto point_at = [&](int32_t r0, int32_t r1) {
+        const bool ok0 = (uint32_t)r0 < Q.rows, ok1 = (uint32_t)r1 < Q.rows;
+        xo0 = ok0 ? (uint32_t)r0 * (FS * 2) : xbytes;
+        xo1 = ok1 ? (uint32_t)r1 * (FS * 2) : xbytes;
+        bad = upper ? !ok1 : !ok0;
     };
-    auto row_of = [&](int s) { return Q.ridx[(int64_t)s * Q.N + ic]; };
+    auto row_of = [&](int s, int c) { return Q.ridx[(int64_t)s * Q.N + c]; };
     const float4 *ug = reinterpret_cast<const float4 *>(Q.u);
     // this wave's slice of LDS holds the hoisted rows of up to USTAGE stages
     float4 *ur = sh.u[wave];
@@ -485,11 +541,12 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
     if (!kIndexed && s0 < s1) {
         // features: copied into this wave's LDS block one stage ahead of the
         // arithmetic and read from there into registers at the stage's start
-        // (each 80-byte row: lane n + 32 hf takes bytes 16 hf, 32 + 16 hf and
-        // 64 + 8 hf); terms: loaded into two alternating register buffers
+        // (of each 80-byte row, lane l reads bytes 16g .. 16g+15 and
+        // 64+4g .. 64+4g+3 of rows r and 16 + r); terms: loaded into two
+        // alternating register buffers
         uint4 *xsw = sh.xs[wave];
         const uint32_t row0 = (uint32_t)tile * TILE_ROWS * (FS * 2);
-        const lds_u2 *xs2 = reinterpret_cast<const lds_u2 *>(xsw);
+        const lds_u1 *xs4 = reinterpret_cast<const lds_u1 *>(xsw);
         float4 tA, tB;
         auto load_t = [&](float4 &t) {
             t = __builtin_bit_cast(float4,
@@ -500,9 +557,10 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
             // an explicit wait, since the compiler's own waits for copies into
             // LDS follow its alias analysis, which need not see this read
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            in.x0 = xsw[5 * n + hf];
-            in.x1 = xsw[5 * n + 2 + hf];
-            in.x2 = xs2[10 * n + 8 + hf];
+            in.x0 = xsw[5 * r + g];
+            in.x1 = xsw[5 * (16 + r) + g];
+            in.x2.x = xs4[20 * r + 16 + g];
+            in.x2.y = xs4[20 * (16 + r) + 16 + g];
             in.t = t;
             in.bad = false;
             // the rows are in registers before the block is refilled
@@ -517,8 +575,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
         for (int s = s0; s < s1; s += 2) {
             if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
             StageIn in;
-            float4 u[4];
-            read_u(u, ur + ((s - s0) % USTAGE) * (H / 4), hf);
+            float4 u[2];
+            read_u(u, ur + ((s - s0) % USTAGE) * (H / 4), g);
             stage_in(in, tA);
             if (s + 1 < s1) {
                 xsoff += xstep;
@@ -527,12 +585,12 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
                 dma_rows(xsw, xr, row0, xsoff, lane);
             }
             asm volatile("" ::: "memory");
-            const float va = stage_math(in, u, hf, w, kp, tab, sum, comp);
-            if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
+            const float va = stage_math(in, u, upper, w, kp, tab, sum, comp);
+            if (kStage && q == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
             if (s + 1 >= s1) break;
 
             if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
-            read_u(u, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf);
+            read_u(u, ur + ((s + 1 - s0) % USTAGE) * (H / 4), g);
             stage_in(in, tB);
             if (s + 2 < s1) {
                 xsoff += xstep;
@@ -541,8 +599,8 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
                 dma_rows(xsw, xr, row0, xsoff, lane);
             }
             asm volatile("" ::: "memory");
-            const float vb = stage_math(in, u, hf, w, kp, tab, sum, comp);
-            if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
+            const float vb = stage_math(in, u, upper, w, kp, tab, sum, comp);
+            if (kStage && q == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
         }
     }
     if (kIndexed && s0 < s1) {
@@ -550,10 +608,13 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
         // flight during the previous stage's arithmetic without copies
         StageIn A, B;
         if (kIndexed) {
-            point_at(row_of(s0));
-            if (s0 + 1 < s1) rnext = row_of(s0 + 1);
+            point_at(row_of(s0, ic0), row_of(s0, ic1));
+            if (s0 + 1 < s1) {
+                rnext0 = row_of(s0 + 1, ic0);
+                rnext1 = row_of(s0 + 1, ic1);
+            }
         }
-        load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
+        load_stage(A, xr, tr, xsoff, tsoff, xo0, xo1, g, to);
         A.bad = bad;
         for (int s = s0; s < s1; s += 2) {
             if ((s - s0) % USTAGE == 0) refill_u(ur, ug, s, min(USTAGE, s1 - s), lane);
@@ -561,18 +622,21 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
                 xsoff += xstep;
                 tsoff += tstep;
                 if (kIndexed) {
-                    point_at(rnext);
-                    if (s + 2 < s1) rnext = row_of(s + 2);
+                    point_at(rnext0, rnext1);
+                    if (s + 2 < s1) {
+                        rnext0 = row_of(s + 2, ic0);
+                        rnext1 = row_of(s + 2, ic1);
+                    }
                 }
             }
-            load_stage(B, xr, tr, xsoff, tsoff, xo, x2o, to);
+            load_stage(B, xr, tr, xsoff, tsoff, xo0, xo1, g, to);
             B.bad = bad;
             // keep the loads here, ahead of their use
             asm volatile("" ::: "memory");
-            float4 u[4];
-            read_u(u, ur + ((s - s0) % USTAGE) * (H / 4), hf);
-            const float va = stage_math(A, u, hf, w, kp, tab, sum, comp);
-            if (kStage && hf == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
+            float4 u[2];
+            read_u(u, ur + ((s - s0) % USTAGE) * (H / 4), g);
+            const float va = stage_math(A, u, upper, w, kp, tab, sum, comp);
+            if (kStage && q == 0 && valid) Q.stage[(int64_t)s * Q.N + i] = va;
             if (s + 1 >= s1) break;
 
             if ((s + 1 - s0) % USTAGE == 0) refill_u(ur, ug, s + 1, min(USTAGE, s1 - s - 1), lane);
@@ -580,25 +644,28 @@ __device__ __forceinline__ void eval_group(const QueryView &Q, int group, int wa
                 xsoff += xstep;
                 tsoff += tstep;
                 if (kIndexed) {
-                    point_at(rnext);
-                    if (s + 3 < s1) rnext = row_of(s + 3);
+                    point_at(rnext0, rnext1);
+                    if (s + 3 < s1) {
+                        rnext0 = row_of(s + 3, ic0);
+                        rnext1 = row_of(s + 3, ic1);
+                    }
                 }
             }
-            load_stage(A, xr, tr, xsoff, tsoff, xo, x2o, to);
+            load_stage(A, xr, tr, xsoff, tsoff, xo0, xo1, g, to);
             A.bad = bad;
             asm volatile("" ::: "memory");
-            read_u(u, ur + ((s + 1 - s0) % USTAGE) * (H / 4), hf);
-            const float vb = stage_math(B, u, hf, w, kp, tab, sum, comp);
-            if (kStage && hf == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
+            read_u(u, ur + ((s + 1 - s0) % USTAGE) * (H / 4), g);
+            const float vb = stage_math(B, u, upper, w, kp, tab, sum, comp);
+            if (kStage && q == 0 && valid) Q.stage[(int64_t)(s + 1) * Q.N + i] = vb;
         }
     }
 
     // combine the parts of each tile in ascending order
     if (P > 1) {
-        if (hf == 0) sh.part[wave][n] = make_float2(sum, comp);
+        if (q == 0) sh.part[wave][n] = make_float2(sum, comp);
         __syncthreads();
     }
-    if (part == 0 && hf == 0 && valid) {
+    if (part == 0 && q == 0 && valid) {
         float S = 0.f, Cc = 0.f;
         for (int p = 0; p < P; ++p) {
             const float2 pc = P > 1 ? sh.part[wave + p][n] : make_float2(sum, comp);
