@@ -7,8 +7,10 @@ from every session (candidates uniform in [16, 4096], bf16 schedule features,
 float32 cost terms), 256 queries in all, submitted with one call and served
 by continuous batching: per-stage rows hoisted once per session ->
 persistent bf16 matrix-core evaluation with Kahan stage sums -> per-query
-top-32 selection, micro-batches overlapping on several streams.  Two steps
-are kept queued so the device never waits for the client.  Inputs are
+top-32 selection, micro-batches overlapping on several streams.  Three steps
+are kept submitted so the device never waits for the client; before the warm-up
+steps the device serves saturated for 100 ms, past the ramp of its power
+state that follows the light-load latency phase.  Inputs are
 resident in HBM before timing (distinct inputs per session and step, several
 GB in all, far above the 256 MB last-level cache).
 
@@ -69,6 +71,10 @@ def parse():
                          "unit, one row-tile group per task)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 65,536 x 64 bf16 / fp8 comparison")
+    ap.add_argument("--settle-ms", type=float, default=100.0,
+                    help="saturated serving before the warm-up steps, in ms (0: none)")
+    ap.add_argument("--queue-depth", type=int, default=3,
+                    help="serving steps the client keeps submitted at a time")
     ap.add_argument("--slots", type=int, default=3, help="serving micro-batches in flight")
     ap.add_argument("--serve-graph", type=int, choices=(0, 1), default=None,
                     help="server steps as a replayed HIP graph (1) or plain launches (0); "
@@ -203,31 +209,33 @@ def main():
     steps_pre = []
     for j in range(args.inputs_per_session):
         ns = [sess_in[s][2][j][0] for s in range(SESSIONS)]
-        sp = [sess_in[s][2][j][1].data_ptr() for s in range(SESSIONS)]
-        tp = [sess_in[s][2][j][2].data_ptr() for s in range(SESSIONS)]
-        steps_pre.append((ns, sp, tp, sum(ns), sum(n * sess_in[s][0] for s, n in enumerate(ns))))
+        sp = np.array([sess_in[s][2][j][1].data_ptr() for s in range(SESSIONS)], np.uint64)
+        tp = np.array([sess_in[s][2][j][2].data_ptr() for s in range(SESSIONS)], np.uint64)
+        steps_pre.append((np.array(ns, np.int32), sp, tp, sum(ns),
+                          sum(n * sess_in[s][0] for s, n in enumerate(ns))))
+    sids_arr = np.array(sids, np.int32)
 
     def submit_step(i):
         ns, sp, tp, _, _ = steps_pre[i % len(steps_pre)]
-        return srv.submit_batch(sids, ns, sp, tp, K)
+        return srv.submit_batch(sids_arr, ns, sp, tp, K)
 
     def run_steps(n):
-        """n steps with two queued ahead; returns (candidates, rows)."""
-        q = [submit_step(0), submit_step(1)] if n > 1 else [submit_step(0)]
+        """n steps, args.queue_depth of them queued at a time; returns
+        (candidates, rows)."""
+        depth = max(1, args.queue_depth)
+        q = [submit_step(i) for i in range(min(depth, n))]
         cands = rows = 0
         for i in range(n):
             srv.wait_all(q.pop(0), 120000)
-            if i + 2 < n:
-                q.append(submit_step(i + 2))
+            if i + depth < n:
+                q.append(submit_step(i + depth))
             cands += steps_pre[i % len(steps_pre)][3]
             rows += steps_pre[i % len(steps_pre)][4]
         return cands, rows
 
     # ------------------------------------------------------------ latency
-    # The open-loop phase runs first: its ~11 s of serving over every input
-    # set also bring the device to its steady state (clocks, and the address
-    # translations of the several GB of inputs), which a saturated phase of a
-    # few dozen steps right after set-up would otherwise partly measure.
+    # The open-loop phase runs first, at light load; the saturated phase
+    # follows it after a settle period (below).
     latency = None
     if not args.no_latency:
         srv.reset_stats()
@@ -259,6 +267,21 @@ def main():
         log(f"latency at {args.latency_qps:.0f} q/s: p50 {ls['p50_us']:.0f} us, "
             f"p99 {ls['p99_us']:.0f} us over {ls['completed']} queries")
     # ------------------------------------------------------------ saturated
+    # Settle: the open-loop phase keeps the device mostly idle, and the first
+    # tens of milliseconds of saturated serving after it run the step kernel
+    # about a quarter slower (about 225 us instead of 177 us per launch, the
+    # device's power state ramping back up).  A saturated server is past that
+    # ramp, so the device serves saturated for at least --settle-ms before the
+    # warm-up steps; the JSON line reports how long.
+    settle = {"ms": 0.0, "steps": 0}
+    if args.settle_ms > 0:
+        t_s = time.perf_counter()
+        while (time.perf_counter() - t_s) * 1e3 < args.settle_ms:
+            run_steps(10)
+            settle["steps"] += 10
+        torch.cuda.synchronize()
+        settle["ms"] = (time.perf_counter() - t_s) * 1e3
+        log(f"settle: {settle['steps']} saturated steps in {settle['ms']:.1f} ms")
     run_steps(args.warmup)
     torch.cuda.synchronize()
     log(f"warm-up done ({args.warmup} steps)")
@@ -567,6 +590,7 @@ def main():
                    "candidates": "uniform [16, 4096] per query",
                    "inputs_per_session": args.inputs_per_session,
                    "input_gb": round(in_bytes / 1e9, 2), "slots": args.slots,
+                   "queue_depth_steps": args.queue_depth,
                    "max_batch_queries": args.max_batch_queries},
         "rows_per_s": rows / wall,
         # algorithmic bytes of every timed launch over the timed wall time:
@@ -574,6 +598,7 @@ def main():
         # micro-batches that a launch's own duration cannot
         "aggregate_gb_per_s": st["kernel_bytes"] / wall / 1e9,
         "latency": latency,
+        "settle_before_warmup": settle,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],

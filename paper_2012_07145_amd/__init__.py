@@ -12,6 +12,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
+from ._lib import REQUEST_DTYPE as _REQUEST_DTYPE
 from ._lib import (CM_BF16, CM_FP8, CM_FP32, CM_MAX_K, CM_N_PARAMS, CM_STAGE_CHUNK,  # noqa: F401
                    CmError, check, lib)
 
@@ -441,13 +442,17 @@ class Server:
         tickets as a uint64 array."""
         n = len(sessions)
         sess = np.ascontiguousarray(sessions, dtype=np.int32)
-        reqs = (_lib.cm_request * max(n, 1))()
-        for j in range(n):
-            reqs[j] = _lib.cm_request(int(n_cands[j]), int(k), ctypes.c_void_p(int(sched_ptrs[j])),
-                                      ctypes.c_void_p(int(terms_ptrs[j])))
+        # the cm_request array filled column by column (one numpy pass per
+        # field instead of a ctypes object per request)
+        reqs = np.zeros(max(n, 1), _REQUEST_DTYPE)
+        reqs["n_cands"][:n] = n_cands
+        reqs["k"][:n] = k
+        reqs["sched"][:n] = np.asarray(sched_ptrs, dtype=np.uint64)
+        reqs["terms"][:n] = np.asarray(terms_ptrs, dtype=np.uint64)
         tickets = np.zeros(max(n, 1), np.uint64)
         check(lib().cm_serve_submit_batch(self.handle, n, sess.ctypes.data_as(ctypes.c_void_p),
-                                          reqs, tickets.ctypes.data_as(ctypes.c_void_p)))
+                                          reqs.ctypes.data_as(ctypes.POINTER(_lib.cm_request)),
+                                          tickets.ctypes.data_as(ctypes.c_void_p)))
         return tickets[:n]
 
     def wait_all(self, tickets, timeout_ms: int = 60000):

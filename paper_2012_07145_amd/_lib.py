@@ -8,6 +8,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcm.so")
 
@@ -87,6 +89,16 @@ class cm_server_cfg(ctypes.Structure):
 class cm_request(ctypes.Structure):
     _fields_ = [("n_cands", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("sched", ctypes.c_void_p), ("terms", ctypes.c_void_p)]
+
+
+# The same layout as a numpy record, for filling request arrays column by
+# column.
+REQUEST_DTYPE = np.dtype({"names": ["n_cands", "k", "sched", "terms"],
+                          "formats": [np.int32, np.int32, np.uint64, np.uint64],
+                          "offsets": [cm_request.n_cands.offset, cm_request.k.offset,
+                                      cm_request.sched.offset, cm_request.terms.offset],
+                          "itemsize": ctypes.sizeof(cm_request)})
+assert ctypes.sizeof(ctypes.c_void_p) == 8 and REQUEST_DTYPE.itemsize == 24
 
 
 class cm_result(ctypes.Structure):
