@@ -41,7 +41,11 @@ BYTES_PER_ROW_BF16 = 40 * 2 + 8 * 4   # schedule features (bf16) + cost terms (f
 BYTES_PER_CAND_OUT = 4                # one float32 cost written per candidate
 K = 32
 SESSIONS = 256
-STEP_SOURCES = ("k_step.hip", "eval_bf16.h", "eval_fp8.h", "topk_dev.h", "cm_internal.h")
+# the step kernel's sources, and the public header whose constants (the stage
+# split) shape its work, as paths from the repository root
+STEP_SOURCES = tuple("paper_2012_07145_amd/csrc/" + f for f in
+                     ("k_step.hip", "eval_bf16.h", "eval_fp8.h", "topk_dev.h", "cm_internal.h")) + (
+                     "include/cm.h",)
 
 
 def log(msg):
@@ -94,7 +98,7 @@ def traffic_record():
     rec = json.load(open(path))
     h = hashlib.sha256()
     for f in STEP_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2012_07145_amd", "csrc", f), "rb").read())
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     if rec.get("kernel_sha256") != h.hexdigest():
         return None
     return rec

@@ -49,7 +49,7 @@ extern "C" {
 #define CM_N_COEFS 8
 #define CM_N_PARAMS 4184     /* float32 parameters, layout in cm_model_create */
 #define CM_MAX_K 256         /* largest beam width of cm_topk_per_query */
-#define CM_STAGE_CHUNK 16    /* sets the stage split of CM_BF16 (see cm_eval_batch) */
+#define CM_STAGE_CHUNK 32    /* sets the stage split of CM_BF16 (see cm_eval_batch) */
 #define CM_STEP_MAX_QUERIES 256 /* queries per cm_step_run */
 #define CM_STATIC_MAX_STAGES 32768 /* stages per cm_eval_batch_static call */
 

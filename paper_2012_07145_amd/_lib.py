@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "CM_OK", -1: "CM_EINVAL", -2: "CM_ENOMEM", -3: "CM_EDEVICE",
 CM_FP32, CM_BF16, CM_FP8 = 0, 1, 2
 CM_MAX_K = 256
 CM_N_PARAMS = 4184
-CM_STAGE_CHUNK = 16
+CM_STAGE_CHUNK = 32
 CM_STEP_MAX_QUERIES = 256
 CM_STATIC_MAX_STAGES = 32768
 

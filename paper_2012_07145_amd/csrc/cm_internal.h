@@ -42,8 +42,8 @@ __host__ __device__ constexpr int stage_parts(int S)
 constexpr int TOPK_TILE = 4096;     // candidates per workgroup of the selection
 
 // bf16 split-product operands of the two dense layers, laid out as the
-// 32x32x16 bf16 matrix-core instruction reads them: 8 bf16 (16 bytes) per
-// lane per operand.  [hi/lo][k-step][lane].
+// 16x16x32 bf16 matrix-core instruction reads them: 8 bf16 (16 bytes) per
+// lane per operand.
 // The bf16 evaluator looks up log2(1 + x) of a feature code in a table of
 // the codes LOG_BASE .. LOG_BASE + LOG_N - 1 (x from 2^-24 to just below
 // 2^40).  Below LOG_BASE, 1 + x rounds to 1 in float32.
