@@ -93,8 +93,15 @@ def test_fp32_with_biases_and_ragged_tail(cm, oracle_mod, model, params):
 
 
 # ------------------------------------------------------------ bf16 path
-@pytest.mark.parametrize("S,N", [(1, 1), (5, 31), (16, 64), (17, 65), (37, 1000), (120, 97)])
+# the bf16 stage split changes above CHUNK / 2, CHUNK and 2 CHUNK stages
+# (CM_STAGE_CHUNK); the sizes straddle each change
+CHUNK = 32
+
+
+@pytest.mark.parametrize("S,N", [(1, 1), (5, 31), (16, 64), (17, 65), (32, 40), (33, 70), (37, 1000),
+                                 (64, 33), (65, 50), (120, 97)])
 def test_bf16_against_fp64_on_rounded_inputs(cm, oracle_mod, model, params, S, N):
+    assert cm.CM_STAGE_CHUNK == CHUNK
     q = draw_query(np.random.default_rng(1000 + S * 7 + N), S, N)
     (c,), batch, cost_t = gc.gpu_costs(cm, model, [q], "bf16")
     qq = gc.quantized(q)
