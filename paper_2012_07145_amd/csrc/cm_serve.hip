@@ -110,6 +110,14 @@ public:
         return true;
     }
 
+    // the slot streams and graphs belong to the server's device: a thread
+    // whose current device is another one leaves the launch to the worker
+    bool launch_here() override
+    {
+        int d = -1;
+        return hipGetDevice(&d) == hipSuccess && d == V_->device;
+    }
+
     int poll(int si, std::string *err) override
     {
         const hipError_t e = hipEventQuery(V_->slot[si].done);

@@ -186,6 +186,7 @@ cm_status Core::submit(int32_t sid, const cm_request *rq, uint64_t *ticket, std:
         return CM_EAGAIN;
     }
     *ticket = enqueue_locked(sid, rq);
+    admit_here_locked();
     cv_work_.notify_one();
     return CM_OK;
 }
@@ -203,6 +204,7 @@ cm_status Core::submit_batch(int32_t n, const int32_t *sessions, const cm_reques
         return CM_EAGAIN;
     }
     for (int32_t j = 0; j < n; ++j) tickets[j] = enqueue_locked(sessions[j], &reqs[j]);
+    admit_here_locked();
     cv_work_.notify_one();
     return CM_OK;
 }
@@ -531,6 +533,20 @@ bool Core::admit_locked(int si)
         retire_locked(si);  // nothing of it runs: release its requests
     }
     return true;
+}
+
+// At an idle server (no micro-batch on the device, the worker asleep), fill
+// the slots from the submitting thread, so that the work is launched without
+// waiting for the worker to wake up (the worker then only watches for the
+// micro-batches' ends).  The same admission as the worker's, under the same
+// lock.  While micro-batches run, the polling worker admits.
+void Core::admit_here_locked()
+{
+    if (fault_ != CM_OK || stop_ || !ex_->launch_here()) return;
+    for (int i = 0; i < cfg_.max_slots; ++i)
+        if (slot_[i].busy) return;
+    for (int i = 0; i < cfg_.max_slots && !pending_.empty(); ++i)
+        if (!slot_[i].busy) admit_locked(i);
 }
 
 void Core::run()

@@ -57,6 +57,9 @@ public:
     // Device clock (microseconds from an arbitrary origin) of that kernel's
     // first wave start and last wave end.
     virtual void kernel_clock(int slot, double *start_us, double *end_us) = 0;
+    // Whether launch() may be called from the calling thread as well as from
+    // the worker (which always may).
+    virtual bool launch_here() { return true; }
 };
 
 // Bytes a request takes from the arena while admitted.
@@ -141,6 +144,7 @@ private:
     void set_fault_locked(const std::string &what);
     void retire_locked(int slot);
     bool admit_locked(int slot);
+    void admit_here_locked();
 
     const cm_server_cfg cfg_;
     Executor *const ex_;

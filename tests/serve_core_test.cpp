@@ -42,6 +42,7 @@ public:
     int delay = 2;                 // polls before a micro-batch finishes
     std::atomic<bool> hold{false}; // keep every micro-batch running
     int fail_poll_at = -1;         // the n-th launch's micro-batch fails
+    std::atomic<bool> here{true};  // launches allowed from a submitting thread
     std::mutex mu;
     std::vector<std::vector<Work>> launches;
     int64_t in_flight_bytes = 0, max_in_flight_bytes = 0;
@@ -90,6 +91,7 @@ public:
         return 1;
     }
     const uint32_t *beam(int si, size_t j) override { return &slot_[si].beams[j * 2 * slot_[si].kb]; }
+    bool launch_here() override { return here; }
     size_t n_launches()
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -455,6 +457,38 @@ void test_stop_drains_the_queue()
     CHECK(core.submit(sid, &q, &t, &e) == CM_ECANCELED);
 }
 
+// A submission to an idle server is launched by the submitting thread
+// before the call returns; with that refused, the worker launches it.  Later
+// submissions, while a micro-batch runs, are the worker's.
+void test_launch_from_submitting_thread()
+{
+    for (bool here : {true, false}) {
+        auto sp = std::make_unique<Server>(config(2, 1 << 30, 1024, 8, 4));
+        Server &s = *sp;
+        s.ex.here = here;
+        s.ex.hold = true;  // nothing finishes until released
+        const int32_t sid = s.open(5);
+        const int32_t sid2 = s.open(7);
+        std::string e;
+        const cm_request q = request(40, 8);
+        uint64_t t1 = 0;
+        CHECK(s.core.submit(sid, &q, &t1, &e) == CM_OK);
+        if (here) CHECK(s.ex.n_launches() == 1);
+        const int32_t sids[2] = {sid, sid2};
+        const cm_request qs[2] = {request(40, 8), request(50, 4)};
+        uint64_t tk[2] = {0, 0};
+        // sid's second request waits for its first; sid2's goes to the other
+        // slot, launched by the worker (a micro-batch is running)
+        CHECK(s.core.submit_batch(2, sids, qs, tk, &e) == CM_OK);
+        s.ex.hold = false;
+        check_result(s.core, t1, 8);
+        check_result(s.core, tk[0], 8);
+        check_result(s.core, tk[1], 4);
+        // (the worker alone may take the first two requests in one batch)
+        if (here) CHECK(s.ex.n_launches() == 3);
+    }
+}
+
 }  // namespace
 
 int main()
@@ -467,6 +501,7 @@ int main()
     test_concurrent_clients();
     test_kernel_busy_time();
     test_stop_drains_the_queue();
+    test_launch_from_submitting_thread();
     std::printf("serve core: all checks passed\n");
     return 0;
 }
