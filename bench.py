@@ -41,11 +41,23 @@ BYTES_PER_ROW_BF16 = 40 * 2 + 8 * 4   # schedule features (bf16) + cost terms (f
 BYTES_PER_CAND_OUT = 4                # one float32 cost written per candidate
 K = 32
 SESSIONS = 256
-# the step kernel's sources, and the public header whose constants (the stage
-# split) shape its work, as paths from the repository root
+# the step kernel's sources, as paths from the repository root; the public
+# header's constants (the stage split among them) shape its work too, so its
+# "#define CM_" lines join the hash (its comments do not)
 STEP_SOURCES = tuple("paper_2012_07145_amd/csrc/" + f for f in
-                     ("k_step.hip", "eval_bf16.h", "eval_fp8.h", "topk_dev.h", "cm_internal.h")) + (
-                     "include/cm.h",)
+                     ("k_step.hip", "eval_bf16.h", "eval_fp8.h", "topk_dev.h", "cm_internal.h"))
+STEP_HEADER = "include/cm.h"
+
+
+def step_kernel_hash():
+    """sha256 over the step kernel's sources and the public header's constants."""
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    for line in open(os.path.join(ROOT, STEP_HEADER), "rb"):
+        if line.startswith(b"#define CM_"):
+            h.update(line)
+    return h.hexdigest()
 
 
 def log(msg):
@@ -96,10 +108,7 @@ def traffic_record():
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in STEP_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("kernel_sha256") != h.hexdigest():
+    if rec.get("kernel_sha256") != step_kernel_hash():
         return None
     return rec
 

@@ -505,7 +505,9 @@ cm_status cm_step_kernel_time(cm_step *step, float *us);
  * A server owns a worker thread, `max_slots` HIP streams each with a
  * persistent step (above), and device pools for its sessions.  Requests are
  * queued by cm_serve_submit and admitted by the worker in submission order
- * as slots and memory free up: a request is admitted when a slot is free,
+ * as slots and memory free up (at an idle server, with no micro-batch on the
+ * device, the submitting call admits and launches them itself when its
+ * thread's current device is the server's): a request is admitted when a slot is free,
  * the device bytes of the admitted, unfinished requests plus its own stay
  * within `arena_bytes`, and its session has no other request in flight (a
  * beam step depends on the previous one; later requests of such a session
@@ -604,7 +606,8 @@ cm_status cm_session_close(cm_server *server, int32_t session);
 cm_status cm_session_beam(cm_server *server, int32_t session, int32_t k, int32_t *idx_host,
                           float *val_host);
 
-/* Queue a request; returns at once with a ticket.  A request takes
+/* Queue a request; returns with a ticket without waiting for the device (at
+ * an idle server the call also launches the request, asynchronously).  A request takes
  * n_stages * n_cands * (80 + 32) + n_cands * 4 + k * 8 bytes of the arena
  * while admitted.  Errors: CM_EINVAL, CM_ENOTFOUND (session), CM_E2BIG (can
  * never be admitted: larger than the arena or a micro-batch, or above
