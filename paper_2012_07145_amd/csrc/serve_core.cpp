@@ -542,9 +542,10 @@ bool Core::admit_locked(int si)
 // lock.  While micro-batches run, the polling worker admits.
 void Core::admit_here_locked()
 {
-    if (fault_ != CM_OK || stop_ || !ex_->launch_here()) return;
+    if (fault_ != CM_OK || stop_) return;
     for (int i = 0; i < cfg_.max_slots; ++i)
         if (slot_[i].busy) return;
+    if (!ex_->launch_here()) return;
     for (int i = 0; i < cfg_.max_slots && !pending_.empty(); ++i)
         if (!slot_[i].busy) admit_locked(i);
 }
