@@ -114,8 +114,11 @@ def test_step_graph_replays_match_eager(cm, model):
     every replay equals the per-call path."""
     import torch
     rng = np.random.default_rng(404)
+    # the second, fourth and sixth groups together straddle every change of the
+    # bf16 stage split (16/17, 32/33, 64/65 stages)
     shapes = [[(5, 100), (40, 700)], [(120, 33), (1, 4096), (17, 17)], [(9, 3000)],
-              [(64, 257), (3, 0), (33, 900), (2, 5)], [(5, 100), (40, 700)]]
+              [(64, 257), (3, 0), (33, 900), (2, 5)], [(5, 100), (40, 700)],
+              [(16, 300), (32, 129), (65, 150), (8, 64)]]
     k = 32
     step = cm.cm_step_create(model, "bf16", max_queries=8, max_stages=512, max_cands=1 << 14,
                              max_k=k, slots=2)
