@@ -328,3 +328,43 @@ def test_serve_forced_launch_failure(cm, model):
     st = srv.stats()
     assert st["completed"] == 1
     srv.close()
+
+
+def test_serve_fp8_equals_alone_and_oracle(cm, oracle_mod):
+    """The FP8 form served (a server created with CM_FP8 over a model with its
+    FP8 form): 30 requests from 6 sessions, submitted together and batched
+    continuously.  Every beam equals the request evaluated alone by
+    cm_eval_batch CM_FP8 + cm_topk_per_query, bit for bit; that selection is
+    the oracle's on the same costs, and the costs stay within the FP8 form's
+    bound of the oracle's FP8 evaluation (Sec. 5.2 under the e4m3 reading)."""
+    import torch
+    from tests import gpucase as gc
+    from tests.test_gpu_fp8 import IN_SCALE, _check_against_oracle
+    act = 8.0
+    params = model_params(bias=True)
+    m = cm.cm_model_create(params)
+    cm.cm_model_prepare_fp8(m, IN_SCALE, act)
+    srv = cm.cm_server_create(m, k=32, max_slots=3, max_sessions=6, max_batch_queries=8,
+                              max_batch_cands=1 << 15, precision="fp8")
+    rng = np.random.default_rng(8080)
+    sess = _sessions(cm, srv, rng, 6)
+    reqs = []
+    for r in range(30):
+        sid, pipe = sess[r % len(sess)]
+        base = draw_query(rng, pipe.shape[0], int(rng.integers(1, 1500)))
+        q = Query(pipe, base.sched, base.terms)
+        codes = oracle_mod.fp8_codes(q.sched, IN_SCALE)
+        sched = torch.from_numpy(np.ascontiguousarray(codes, np.uint8).ravel()).cuda()
+        terms = torch.from_numpy(np.ascontiguousarray(q.terms, np.float32).ravel()).cuda()
+        reqs.append((sid, q, codes, sched, terms, (1, 8, 32)[r % 3]))
+    tickets = [srv.submit(sid, q.n_cands, sched, terms, k)
+               for sid, q, _, sched, terms, k in reqs]
+    for t, (sid, q, codes, _, _, k) in zip(tickets, reqs):
+        idx, val, _ = srv.wait(int(t), 60000)
+        (c,), batch, cost_t = gc.gpu_costs_fp8(cm, m, [q], [codes])
+        ai, av = gc.gpu_topk(cm, cost_t, batch, k)
+        assert np.array_equal(idx, ai[0]) and _same(val, av[0]), (sid, q.n_stages, q.n_cands)
+        gc.assert_select_bit_exact(oracle_mod, c, idx, val, k)
+        _check_against_oracle(oracle_mod, params, act, q, codes, c)
+    srv.close()
+    m.close()
