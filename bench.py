@@ -624,6 +624,9 @@ def main():
                            "kernel": "k_step_fp8",
                            "achieved_gb_per_s": bytes8 / (dev8 * 1e-6) / 1e9 if dev8 else None,
                            "frac_of_hbm_peak": bytes8 / (dev8 * 1e-6) / 1e9 / HBM_PEAK_GBS if dev8 else None,
+                           "launches": st8["micro_batches"],
+                           "algorithmic_bytes_per_launch": bytes8 / max(1, st8["micro_batches"]),
+                           "device_us_per_launch": dev8 / max(1, st8["micro_batches"]),
                            "scales": {"s_in": f8_in, "s_h": f8_h},
                            "seconds": time.perf_counter() - t_f8}
             srv8.close()
