@@ -288,6 +288,21 @@ def main():
     # device's power state ramping back up).  A saturated server is past that
     # ramp, so the device serves saturated for at least --settle-ms before the
     # warm-up steps; the JSON line reports how long.
+    # for the record, 20 steps timed right after the light-load phase, before
+    # the settle period (the same measure as the headline's)
+    cold = None
+    if not args.no_latency:
+        srv.reset_stats()
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        c_cold, _ = run_steps(20)
+        torch.cuda.synchronize()
+        w_c = time.perf_counter() - t_c
+        sc = srv.stats()
+        dev_c = sc["kernel_busy_us"] if sc["kernel_busy_launches"] == sc["micro_batches"] else sc["kernel_us"]
+        cold = {"steps": 20, "candidates_per_s": c_cold / w_c, "ms_per_step": w_c / 20 * 1e3,
+                "roofline_frac": sc["kernel_bytes"] / (dev_c * 1e-6) / 1e9 / HBM_PEAK_GBS if dev_c else None}
+        log(f"cold: {cold['candidates_per_s']:.3e} candidates/s, frac {cold['roofline_frac']:.3f}")
     settle = {"ms": 0.0, "steps": 0}
     if args.settle_ms > 0:
         t_s = time.perf_counter()
@@ -692,6 +707,7 @@ def main():
         "aggregate_gb_per_s": st["kernel_bytes"] / wall / 1e9,
         "latency": latency,
         "settle_before_warmup": settle,
+        "serving_cold": cold,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],
