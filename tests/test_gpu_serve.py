@@ -368,3 +368,46 @@ def test_serve_fp8_equals_alone_and_oracle(cm, oracle_mod):
         _check_against_oracle(oracle_mod, params, act, q, codes, c)
     srv.close()
     m.close()
+
+
+def test_serve_concurrent_client_threads(cm, model):
+    """Four client threads submit and wait at once (the C calls release the
+    interpreter lock), so launches come from several submitting threads and
+    the worker; every beam equals the request evaluated alone."""
+    import threading
+    rng = np.random.default_rng(4242)
+    k = 16
+    srv = cm.cm_server_create(model, k=k, max_slots=3, max_sessions=8, max_batch_queries=4)
+    sess = _sessions(cm, srv, rng, 8, smax=60)
+    work = []
+    for c in range(4):
+        mine = []
+        for r in range(8):
+            sid, pipe = sess[(2 * c + r % 2)]
+            base = draw_query(rng, pipe.shape[0], int(rng.integers(1, 900)))
+            q = Query(pipe, base.sched, base.terms)
+            mine.append((sid, q) + _device_inputs(q))
+        work.append(mine)
+    results = [[None] * 8 for _ in range(4)]
+    errors = []
+
+    def client(c):
+        try:
+            for j, (sid, q, sched, terms) in enumerate(work[c]):
+                t = srv.submit(sid, q.n_cands, sched, terms, k)
+                results[c][j] = srv.wait(t, 60000)[:2]
+        except Exception as exc:  # reported below, in the test's thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(120)
+    assert not errors, errors
+    for c in range(4):
+        for j, (sid, q, _, _) in enumerate(work[c]):
+            idx, val = results[c][j]
+            ri, rv = _alone(cm, model, q, k)
+            assert np.array_equal(idx, ri) and _same(val, rv), (c, j, sid)
+    srv.close()
