@@ -179,7 +179,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the cost-model path shards by session across "
-              "GPUs with no feature exchange, and this build measures one GPU's share. "
+              "GPUs with no feature exchange, and the benchmark measures one GPU's share. "
               f"--gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
 
